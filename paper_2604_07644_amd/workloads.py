@@ -1,0 +1,271 @@
+"""Seeded synthetic stage-structured LTV-QP and SLS workloads.
+
+These generators stand in for the paper's robot workloads (the MuJoCo quadruped
+and humanoid models of Sec. V-C / App. E are not available): they produce
+problems of the same shapes (state dimension, control dimension, horizon,
+constraint rows per stage) and the scale stated in the abstract (about 2e5
+decision variables and 8e4 constraints).  The problem data follow the LTV-QP
+of Sec. III-B, eq. (sqp_qp): dynamics x_{k+1} = A_k x_k + B_k u_k + b_k, stage
+costs (Q_k, S_k, R_k, q_k, r_k), terminal cost (Q_N, q_N), and two-sided
+constraint rows  l <= C_k x_k + D_k u_k <= u  (one-sided rows use l = -inf,
+which is the paper's  z <= f  form), terminal rows  l <= C_N x_N <= u.
+
+This module holds input generation only: random draws, the zero-input
+roll-out used to make the drawn polytopes feasible, and packing.  It contains
+none of the solver's arithmetic and is shared by the tests, the benchmark and
+the smoke check.
+
+Random draws use ``numpy.random.default_rng([cfg_id, instance_id])``.  In
+``N(0, v)`` the second argument is a variance.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import numpy as np
+
+INF = float("inf")
+
+
+@dataclass
+class QPProblem:
+    """One stage-structured LTV-QP, all arrays float64, row-major."""
+    N: int
+    nx: int
+    nu: int
+    nc: int
+    nf: int
+    A: np.ndarray   # [N, nx, nx]
+    B: np.ndarray   # [N, nx, nu]
+    b: np.ndarray   # [N, nx]
+    Q: np.ndarray   # [N+1, nx, nx]
+    R: np.ndarray   # [N, nu, nu]
+    S: np.ndarray   # [N, nu, nx]
+    q: np.ndarray   # [N+1, nx]
+    r: np.ndarray   # [N, nu]
+    C: np.ndarray   # [N, nc, nx]
+    D: np.ndarray   # [N, nc, nu]
+    CN: np.ndarray  # [nf, nx]
+    l: np.ndarray   # [N*nc + nf]
+    u: np.ndarray   # [N*nc + nf]
+    x0: np.ndarray  # [nx]
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def m(self) -> int:
+        return self.N * self.nc + self.nf
+
+    def copy(self) -> "QPProblem":
+        kw = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in self.__dict__.items()}
+        kw["meta"] = dict(self.meta)
+        return QPProblem(**kw)
+
+
+def _rng(cfg_id: int, instance_id: int) -> np.random.Generator:
+    return np.random.default_rng([int(cfg_id), int(instance_id)])
+
+
+def _normal(rng, var, shape):
+    return rng.standard_normal(shape) * np.sqrt(var)
+
+
+def _spectral_clip(A: np.ndarray, rmax: float) -> np.ndarray:
+    rad = np.max(np.abs(np.linalg.eigvals(A)))
+    return A * (rmax / rad) if rad > rmax else A
+
+
+def _box_rows(nx: int, nu: int):
+    C = np.zeros((nx + nu, nx))
+    D = np.zeros((nx + nu, nu))
+    C[:nx, :nx] = np.eye(nx)
+    D[nx:, :] = np.eye(nu)
+    return C, D
+
+
+def _draw_x0(rng, nx, var, xmax=None):
+    while True:
+        x0 = _normal(rng, var, nx)
+        if xmax is None or np.max(np.abs(x0)) <= xmax:
+            return x0
+
+
+def box_lq(N=32, nx=4, nu=2, cfg_id=0, instance_id=0, xmax=5.0, umax=1.0,
+           a_scale=0.05, b_var=0.1, terminal_box=True) -> QPProblem:
+    """Box-constrained LQ QP (the plain-ADMM workload: nx=4, nu=2, N=32).
+
+    A_t = I + a_scale*G_t, G_t ~ N(0, 1/nx); B_t ~ N(0, b_var); Q_t = diag U[1,10];
+    R_t = diag U[0.1,1]; q = r = 0; S = 0; b = 0; |x| <= xmax, |u| <= umax per
+    stage and |x_N| <= xmax at the terminal stage; x0 ~ N(0,1), redrawn until
+    |x0|_inf <= xmax.  Per stage the draw order is A, B, Q, R; then Q_N, x0.
+    """
+    rng = _rng(cfg_id, instance_id)
+    A = np.empty((N, nx, nx)); B = np.empty((N, nx, nu))
+    Q = np.zeros((N + 1, nx, nx)); R = np.zeros((N, nu, nu))
+    for t in range(N):
+        A[t] = np.eye(nx) + a_scale * _normal(rng, 1.0 / nx, (nx, nx))
+        B[t] = _normal(rng, b_var, (nx, nu))
+        Q[t] = np.diag(rng.uniform(1.0, 10.0, nx))
+        R[t] = np.diag(rng.uniform(0.1, 1.0, nu))
+    Q[N] = np.diag(rng.uniform(1.0, 10.0, nx))
+    x0 = _draw_x0(rng, nx, 1.0, xmax)
+    Cb, Db = _box_rows(nx, nu)
+    nc = nx + nu
+    C = np.broadcast_to(Cb, (N, nc, nx)).copy()
+    D = np.broadcast_to(Db, (N, nc, nu)).copy()
+    lo = np.concatenate([-xmax * np.ones(nx), -umax * np.ones(nu)])
+    hi = -lo
+    nf = nx if terminal_box else 0
+    CN = np.eye(nx) if terminal_box else np.zeros((0, nx))
+    l = np.concatenate([np.tile(lo, N), -xmax * np.ones(nf)])
+    u = np.concatenate([np.tile(hi, N), xmax * np.ones(nf)])
+    return QPProblem(N, nx, nu, nc, nf, A, B, np.zeros((N, nx)), Q, R,
+                     np.zeros((N, nu, nx)), np.zeros((N + 1, nx)), np.zeros((N, nu)),
+                     C, D, CN, l, u, x0,
+                     meta=dict(kind="box_lq", cfg_id=cfg_id, instance_id=instance_id,
+                               xmax=xmax, umax=umax))
+
+
+def polytopic_lq(N, nx, nu, nc=40, cfg_id=1, instance_id=0, a_scale=0.02,
+                 a_var=None, b_var=0.05, x0_var=0.25, rho_max=1.05, ref_var=1.0,
+                 shared_dynamics_seed=None) -> QPProblem:
+    """Time-varying LQ QP with random polytopic stage constraints.
+
+    A_t = I + a_scale*M_t, M_t ~ N(0, 1/nx), rescaled so its spectral radius is
+    at most rho_max; B_t ~ N(0, b_var); Q_t = diag U[1,10]; R_t = diag U[0.1,1].
+    Per stage, nc rows [C_t D_t] drawn N(0,1) and normalised to unit 2-norm;
+    upper bounds d_t = s_t + (C_t xbar_t)^+ with s_t ~ U[0.5, 2] and xbar the
+    zero-input roll-out from x0 (so u = 0 is strictly feasible); l = -inf.
+    No terminal rows.  x0 ~ N(0, x0_var).
+
+    Linear costs come from a constant tracking reference x_ref ~ N(0, ref_var):
+    q_t = -Q_t x_ref (t = 0..N), r_t = 0, i.e. the stage cost is
+    1/2 (x - x_ref)^T Q (x - x_ref) up to a constant.  An SQP linearisation
+    produces such non-zero gradients; without them the optimum stays near the
+    origin and no drawn row is ever active.  x_ref is drawn after x0 (from the
+    shared seed when ``shared_dynamics_seed`` is given).
+
+    With ``shared_dynamics_seed`` the stage data are drawn from that seed and
+    only x0 from (cfg_id, instance_id): a batch of instances that differ only
+    in their initial state.
+    """
+    a_var = 1.0 / nx if a_var is None else a_var
+    rng = _rng(cfg_id, instance_id if shared_dynamics_seed is None else shared_dynamics_seed)
+    A = np.empty((N, nx, nx)); B = np.empty((N, nx, nu))
+    Q = np.zeros((N + 1, nx, nx)); R = np.zeros((N, nu, nu))
+    C = np.empty((N, nc, nx)); D = np.empty((N, nc, nu)); s = np.empty((N, nc))
+    for t in range(N):
+        A[t] = _spectral_clip(np.eye(nx) + a_scale * _normal(rng, a_var, (nx, nx)), rho_max)
+        B[t] = _normal(rng, b_var, (nx, nu))
+        Q[t] = np.diag(rng.uniform(1.0, 10.0, nx))
+        R[t] = np.diag(rng.uniform(0.1, 1.0, nu))
+        G = rng.standard_normal((nc, nx + nu))
+        G /= np.linalg.norm(G, axis=1, keepdims=True)
+        C[t] = G[:, :nx]; D[t] = G[:, nx:]
+        s[t] = rng.uniform(0.5, 2.0, nc)
+    Q[N] = np.diag(rng.uniform(1.0, 10.0, nx))
+    xref = _normal(rng, ref_var, nx) if shared_dynamics_seed is not None else None
+    if shared_dynamics_seed is not None:
+        rng = _rng(cfg_id, instance_id)
+    x0 = _normal(rng, x0_var, nx)
+    if xref is None:
+        xref = _normal(rng, ref_var, nx)
+    q = -np.einsum("tij,j->ti", Q, xref)
+    xbar = x0.copy(); d = np.empty((N, nc))
+    with np.errstate(over="ignore", invalid="ignore"):
+        for t in range(N):
+            d[t] = s[t] + np.maximum(C[t] @ xbar, 0.0)
+            xbar = A[t] @ xbar
+    d[~np.isfinite(d)] = INF
+    l = -INF * np.ones(N * nc); u = d.reshape(-1).copy()
+    return QPProblem(N, nx, nu, nc, 0, A, B, np.zeros((N, nx)), Q, R,
+                     np.zeros((N, nu, nx)), q, np.zeros((N, nu)),
+                     C, D, np.zeros((0, nx)), l, u, x0,
+                     meta=dict(kind="polytopic_lq", cfg_id=cfg_id, instance_id=instance_id,
+                               xref=xref))
+
+
+def quadruped_qp(instance_id=0) -> QPProblem:
+    """Quadruped-shaped QP: nx=61, nu=12, N=128, 40 polytopic rows per stage."""
+    return polytopic_lq(128, 61, 12, 40, cfg_id=1, instance_id=instance_id,
+                        a_scale=0.02, b_var=0.05, x0_var=0.25, rho_max=1.05)
+
+
+def humanoid_qp(instance_id=0, N=2048) -> QPProblem:
+    """Humanoid-shaped QP at the paper's scale: nx=75, nu=19, N=2048, 40 rows
+    per stage (192,587 variables, 81,920 rows).  Dynamics, costs and x0 as in
+    the box workload (A = I + 0.05 G, B ~ N(0, 0.1), x0 ~ N(0, 1))."""
+    return polytopic_lq(N, 75, 19, 40, cfg_id=2, instance_id=instance_id,
+                        a_scale=0.05, b_var=0.1, x0_var=1.0, rho_max=1.05)
+
+
+def sls_batch(count=64, N=64, nx=61, nu=12, nc=40, e_var=0.01, cfg_id=3):
+    """SLS workload: one quadruped-shaped polytopic QP (shared stage data) and
+    ``count`` initial states, plus disturbance maps E_t ~ N(0, e_var) and the
+    disturbance bound |w|_inf <= 0.01."""
+    probs = [polytopic_lq(N, nx, nu, nc, cfg_id=cfg_id, instance_id=i, a_scale=0.02,
+                          b_var=0.05, x0_var=0.25, rho_max=1.05,
+                          shared_dynamics_seed=10 ** 9) for i in range(count)]
+    rng = _rng(cfg_id, 10 ** 9 + 1)
+    E = _normal(rng, e_var, (N, nx, nx))
+    return probs, E, 0.01
+
+
+NX_CLASSES = (12, 36, 61, 75)
+NU_CLASSES = (4, 12, 19)
+
+
+def uneven_batch(count=512, cfg_id=4, first_instance=0, nmin=16, nmax=512):
+    """Batch of box-constrained QPs of uneven shape: nx in {12,36,61,75},
+    nu in {4,12,19} drawn independently and uniformly, N ~ U{nmin..nmax};
+    per-instance bound scales xmax ~ U[3,7], umax ~ U[0.5,1.5]; stage data as
+    in the box workload."""
+    out = []
+    for i in range(first_instance, first_instance + count):
+        rng = _rng(cfg_id, i)
+        nx = int(rng.choice(NX_CLASSES)); nu = int(rng.choice(NU_CLASSES))
+        N = int(rng.integers(nmin, nmax + 1))
+        xmax = float(rng.uniform(3.0, 7.0)); umax = float(rng.uniform(0.5, 1.5))
+        p = box_lq(N=N, nx=nx, nu=nu, cfg_id=cfg_id, instance_id=10 ** 7 + i,
+                   xmax=xmax, umax=umax, terminal_box=True)
+        p.meta.update(dict(kind="uneven", batch_index=i))
+        out.append(p)
+    return out
+
+
+def random_small(N, nx, nu, nc, nf, seed, general=True, b_nonzero=True, s_nonzero=True,
+                 q_nonzero=True, lower=True):
+    """Small random strictly convex LTV-QP with every term present (S, b, q, r,
+    two-sided rows, terminal rows) for parity tests of the general path."""
+    rng = np.random.default_rng([99, seed])
+    A = np.eye(nx) + 0.3 * rng.standard_normal((N, nx, nx)) / np.sqrt(nx)
+    B = rng.standard_normal((N, nx, nu)) * 0.5
+    b = rng.standard_normal((N, nx)) * 0.1 if b_nonzero else np.zeros((N, nx))
+    Q = np.empty((N + 1, nx, nx)); R = np.empty((N, nu, nu)); S = np.zeros((N, nu, nx))
+    for t in range(N + 1):
+        M = rng.standard_normal((nx, nx)); Q[t] = M @ M.T / nx + 0.5 * np.eye(nx)
+    for t in range(N):
+        M = rng.standard_normal((nu, nu)); R[t] = M @ M.T / nu + 0.5 * np.eye(nu)
+        if s_nonzero:
+            # keep [[Q S^T],[S R]] positive definite: S small relative to Q, R
+            S[t] = 0.1 * rng.standard_normal((nu, nx))
+    q = rng.standard_normal((N + 1, nx)) * (0.5 if q_nonzero else 0.0)
+    r = rng.standard_normal((N, nu)) * (0.5 if q_nonzero else 0.0)
+    C = rng.standard_normal((N, nc, nx)); D = rng.standard_normal((N, nc, nu))
+    CN = rng.standard_normal((nf, nx))
+    m = N * nc + nf
+    x0 = rng.standard_normal(nx) * 0.3
+    # bounds around the row values of a random roll-out, so the QP is feasible
+    ub = rng.standard_normal((N, nu)) * 0.3
+    xb = x0.copy(); vb = np.empty(m)
+    for t in range(N):
+        vb[t * nc:(t + 1) * nc] = C[t] @ xb + D[t] @ ub[t]
+        xb = A[t] @ xb + B[t] @ ub[t] + b[t]
+    vb[N * nc:] = CN @ xb
+    hi = vb + rng.uniform(0.05, 0.6, m)
+    lo = vb - rng.uniform(0.05, 0.6, m) if lower else -INF * np.ones(m)
+    if lower:
+        # a few one-sided and a few unbounded rows
+        k = rng.random(m)
+        lo[k < 0.2] = -INF
+        hi[(k > 0.9)] = INF
+    return QPProblem(N, nx, nu, nc, nf, A, B, b, Q, R, S, q, r, C, D, CN, lo, hi, x0,
+                     meta=dict(kind="random_small", seed=seed))

@@ -1,0 +1,207 @@
+/*
+ * gsls.h -- C ABI of the MI355X (gfx950) ADMM / associative-scan QP and SLS
+ * solver of GPU-SLS (Fang & Chou, "Safe Large-Scale Robust Nonlinear MPC in
+ * Milliseconds via Reachability-Constrained System Level Synthesis on the GPU").
+ *
+ * Conventions shared by every entry point
+ *  - Arrays are row-major double precision.  Host or device memory as selected
+ *    by gsls_qp_desc.mem (device pointers are read on the handle's stream).
+ *  - Every input is copied during the call that receives it; the library never
+ *    keeps a caller pointer after a call returns.  Output buffers belong to the
+ *    caller; their sizes follow from the dimensions.
+ *  - Return value: GSLS_OK (0) or a negative GSLS_ERR_* code; no C++ exception
+ *    crosses the ABI.  gsls_strerror() names a code.
+ *  - A handle is not thread-safe; distinct handles may be used concurrently on
+ *    distinct streams.
+ *
+ * Problem (Sec. III-B, eq. (sqp_qp); the ADMM split of Sec. IV-A, eq. (admm_qp)):
+ *   min  sum_{k<N} 1/2 [x;u]^T [[Q_k S_k^T];[S_k R_k]] [x;u] + q_k^T x + r_k^T u
+ *        + 1/2 x_N^T Q_N x_N + q_N^T x_N
+ *   s.t. x_{k+1} = A_k x_k + B_k u_k + b_k,  x_0 = x0,
+ *        l_k <= C_k x_k + D_k u_k <= u_k  (nc rows per stage),
+ *        l_N <= C_N x_N <= u_N            (nf terminal rows).
+ * The paper's one-sided rows  z <= f  are the case l = -inf.  Infinite bounds
+ * are allowed.  Q_k, R_k are symmetric; the augmented costs must stay positive
+ * definite (R_k + rho D_k^T D_k > 0, and the Riccati matrices
+ * R_hat + B^T P B > 0), else GSLS_ERR_NOT_PD.
+ */
+#ifndef GSLS_H
+#define GSLS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ return codes */
+enum {
+  GSLS_OK = 0,
+  GSLS_ERR_INVALID_ARG = -1, /* null pointer, non-finite data, l > u, bad setting */
+  GSLS_ERR_DIM = -2,         /* dimensions out of the supported range          */
+  GSLS_ERR_NOT_PD = -3,      /* a Cholesky factor failed (matrix not pos. def.) */
+  GSLS_ERR_NUMERICAL = -4,   /* NaN/Inf met during the solve                    */
+  GSLS_ERR_OOM = -5,         /* device allocation failed                        */
+  GSLS_ERR_HIP = -6,         /* HIP runtime error (no device, launch failure)   */
+  GSLS_ERR_STATE = -7        /* call out of order (e.g. get before solve)       */
+};
+
+/* solver outcome in gsls_result.status */
+enum {
+  GSLS_SOLVED = 1,           /* r_p <= tol and r_d <= tol                      */
+  GSLS_MAX_ITER = 2,         /* iteration limit reached                         */
+  GSLS_NUMERICAL_FAIL = 3    /* NaN/Inf in the residuals                        */
+};
+
+/* memory kinds */
+enum { GSLS_HOST = 0, GSLS_DEVICE = 1 };
+
+/* precision modes */
+enum {
+  GSLS_MIXED = 0,  /* FP32 scan products and iteration; FP64 Cholesky/LU factors */
+  GSLS_FP64 = 1    /* everything in FP64                                          */
+};
+
+/* Supported dimensions (per instance). */
+#define GSLS_MAX_NX 80
+#define GSLS_MAX_NU 32
+#define GSLS_MAX_NC 64
+#define GSLS_MAX_N 65536
+
+/* One LTV-QP.  Pointer shapes (row-major):
+ *   A [N][nx][nx]  B [N][nx][nu]  b [N][nx] (NULL => 0)
+ *   Q [N+1][nx][nx]  R [N][nu][nu]  S [N][nu][nx] (NULL => 0)
+ *   q [N+1][nx] (NULL => 0)  r [N][nu] (NULL => 0)
+ *   C [N][nc][nx]  D [N][nc][nu]  CN [nf][nx] (NULL iff nf == 0)
+ *   l, u [N*nc + nf]  (stage rows k*nc..k*nc+nc-1, then the nf terminal rows) */
+typedef struct gsls_qp_desc {
+  int32_t N, nx, nu, nc, nf;
+  int32_t mem;
+  const double *A, *B, *b;
+  const double *Q, *R, *S;
+  const double *q, *r;
+  const double *C, *D, *CN;
+  const double *l, *u;
+} gsls_qp_desc;
+
+/* Solver settings; gsls_default_settings() fills the defaults in brackets. */
+typedef struct gsls_settings {
+  int32_t precision;     /* GSLS_MIXED or GSLS_FP64                       [MIXED] */
+  int32_t max_iter;      /* ADMM iteration limit                          [10000] */
+  int32_t adaptive_rho;  /* OSQP-style rho adaptation on/off                  [1] */
+  int32_t sigma;         /* rho is reconsidered every sigma iterations       [25] */
+  double rho_min;        /* clamp                                          [1e-6] */
+  double rho_max;        /*                                                [1e6]  */
+  double rho_tol;        /* change rho only if it moves by more than this   [5.0] */
+  int32_t chunks_epoch;  /* horizon chunks for the factor scan (0 = auto)     [0] */
+  int32_t chunks_iter;   /* horizon chunks for the iteration scans (0 = auto) [0] */
+} gsls_settings;
+
+/* Outcome of one solve. */
+typedef struct gsls_result {
+  int32_t status;        /* GSLS_SOLVED / GSLS_MAX_ITER / GSLS_NUMERICAL_FAIL     */
+  int32_t iterations;    /* ADMM iterations (x-updates) performed                 */
+  int32_t rho_updates;   /* number of rho changes (each costs a factor epoch)     */
+  int32_t factorizations;/* factor epochs run                                     */
+  double r_p;            /* |G xi - z|_inf at the last iteration                  */
+  double r_d;            /* rho |G^T (z+ - z)|_inf at the last iteration          */
+  double rho;            /* final rho                                             */
+  double ms_total;       /* device time of the whole solve (HIP events)           */
+  double ms_factor;      /* device time spent in factor epochs                    */
+  double ms_iterate;     /* device time spent in the ADMM iteration kernel        */
+} gsls_result;
+
+typedef struct gsls_qp gsls_qp;
+
+void gsls_default_settings(gsls_settings* s);
+const char* gsls_strerror(int code);
+
+/* Host-only validation of a problem description (no device call): dimensions,
+ * null pointers, finiteness, l <= u.  Host memory only.  Returns GSLS_OK or the
+ * code gsls_qp_setup would return for the same description. */
+int gsls_validate_desc(const gsls_qp_desc* desc);
+
+/* Create a solver handle for one QP (Sec. IV-A).  Copies the problem data to
+ * the device, converts it to the working precision and allocates the caches.
+ * stream: hipStream_t to enqueue on (NULL = default stream).
+ * settings: NULL = defaults.  On success *out receives the handle. */
+int gsls_qp_setup(const gsls_qp_desc* desc, const gsls_settings* settings, void* stream,
+                  gsls_qp** out);
+
+/* Replace the bounds l, u (length N*nc + nf, same memory kind as the setup)
+ * without touching the factorisation: used to tighten rows by SLS margins. */
+int gsls_qp_update_bounds(gsls_qp* h, const double* l, const double* u);
+
+/* ADMM solve (Sec. III-C / IV-A) from a cold start z = y = 0.
+ * x0 [nx] initial state; rho initial penalty (> 0); tol absolute tolerance on
+ * both r_p = |G xi - z|_inf and r_d = rho |G^T (z+ - z)|_inf.  Each ADMM
+ * x-update is the LQR subproblem eq. (primal_update), solved by the reverse
+ * associative scan of eq. (combination_rules) / eq. (controller_cache) and the
+ * forward composition eq. (nom_recovery), with the rho-invariant factors cached
+ * across iterations.  Blocks until the solve is finished; result may be NULL. */
+int gsls_qp_solve(gsls_qp* h, const double* x0, double rho, double tol, gsls_result* result);
+
+/* As gsls_qp_solve, starting from the iterate (z0, y0) (length N*nc + nf each,
+ * y0 the scaled dual lambda/rho at penalty rho). */
+int gsls_qp_solve_warm(gsls_qp* h, const double* x0, double rho, double tol,
+                       const double* z0, const double* y0, gsls_result* result);
+
+/* Copy the last solution to host buffers (any may be NULL):
+ * X [N+1][nx], U [N][nu], z [N*nc+nf], lambda [N*nc+nf] (= rho * y). */
+int gsls_qp_get(gsls_qp* h, double* X, double* U, double* z, double* lambda);
+
+void gsls_qp_free(gsls_qp* h);
+
+/* Diagnostics.  enable = 1 / 0 switches per-phase cycle counting of the ADMM
+ * iteration kernel on or off (-1 leaves it unchanged; counting adds one
+ * barrier per phase).  cycles16 (nullable) receives the accumulated shader
+ * clock cycles of workgroup 0 per phase since the last read:
+ * [1] linear terms, [2] backward chunk fold, [3] backward doubling exchange,
+ * [4] backward fix-up and gains, [5] forward chunk fold, [6] forward doubling
+ * exchange, [7] forward fix-up + projection + dual update, [8] residual
+ * reduction; the counters are then cleared.  layout4 (nullable) receives the
+ * factor-scan chunk count, the iteration chunk (workgroup) count, whether the
+ * chunk operators are LDS-resident, and the largest chunk length. */
+int gsls_debug_phase_cycles(gsls_qp* h, int32_t enable, double* cycles16, int32_t* layout4);
+
+/* ----------------------------------------------------------------- SLS ---
+ * Controller synthesis eq. (fastsls_qp) of Sec. III-D / IV-B on the handle's
+ * dynamics (A_k, B_k) and constraint rows (C_k, D_k, C_N).
+ *  E      [N][nx][nx] disturbance maps E_j (Phi^x_{j+1,j} = E_j).
+ *  tau    weights of eq. (sls_cost_matrices_tau): [N][N][nc] stage part
+ *         tau[k][j][.] (read for j < k <= N-1) followed by [N][nf] terminal part
+ *         tau_N[j][.].  NULL => all zero.
+ *  Qbar [nx][nx], Rbar [nu][nu], QbarN [nx][nx]: symmetric positive definite.
+ *  rownorm 2: margins for |w_j|_2 <= wbound (the paper's row 2-norm);
+ *          1: margins for |w_j|_inf <= wbound (row 1-norm, the dual norm).
+ *  Outputs (host memory, any may be NULL):
+ *   Phi_x: N(N+1)/2 blocks [nx][nx]; column j holds k = j+1..N at block offset
+ *          j*N - j(j-1)/2.
+ *   Phi_u: N(N-1)/2 blocks [nu][nx]; column j holds k = j+1..N-1 at block
+ *          offset j*(N-1) - j(j-1)/2.
+ *   h [N][nc]: h_k = wbound * sum_{j<k} rownorm(C_k Phi^x_{k,j} + D_k Phi^u_{k,j}).
+ *   hf [nf]:  hf = wbound * sum_{j<N} rownorm(C_N Phi^x_{N,j}).
+ * Column j's LQR runs over stages j+1..N-1 with terminal cost at N. */
+int gsls_sls_solve(gsls_qp* h, const double* E, const double* tau, const double* Qbar,
+                   const double* Rbar, const double* QbarN, int32_t rownorm, double wbound,
+                   double* Phi_x, double* Phi_u, double* hmarg, double* hf);
+
+/* Batched SLS: `count` instances sharing the handle's stage data, E and the
+ * cost weights, each with its own tau (count consecutive tau arrays).  Outputs
+ * h [count][N][nc], hf [count][nf]; Phi not returned.  Device time of the
+ * batch is written to *ms if ms != NULL. */
+int gsls_sls_solve_batch(gsls_qp* h, int32_t count, const double* E, const double* tau,
+                         const double* Qbar, const double* Rbar, const double* QbarN,
+                         int32_t rownorm, double wbound, double* hmarg, double* hf, double* ms);
+
+/* Dual weights of App. B from multipliers lambda [N*nc+nf] and the responses
+ * of gsls_sls_solve (host memory): tau_{k,j} = |lambda_k| / sqrt(beta_{k,j} + eps),
+ * beta the squared row norms of C_k Phi^x_{k,j} + D_k Phi^u_{k,j}.  tau has the
+ * layout of gsls_sls_solve's tau (entries with k <= j set to 0). */
+int gsls_sls_tau(gsls_qp* h, const double* lambda, const double* Phi_x, const double* Phi_u,
+                 double eps, double* tau);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSLS_H */

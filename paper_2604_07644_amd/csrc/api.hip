@@ -1,0 +1,586 @@
+// Host side of the C ABI declared in include/gsls.h: argument validation,
+// handle lifetime, device buffers, the rho / factor-epoch driver around the
+// persistent ADMM iteration kernel, and the result struct.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <type_traits>
+#include <vector>
+
+#include "dev_common.hpp"
+#include "solver.hpp"
+
+namespace gsls {
+
+// ------------------------------------------------------------- allocation
+struct DevArena {
+  std::vector<void*> ptrs;
+  bool ok = true;
+  template <typename T>
+  T* alloc(size_t n) {
+    if (n == 0) n = 1;
+    void* p = nullptr;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) { ok = false; return nullptr; }
+    ptrs.push_back(p);
+    return (T*)p;
+  }
+  ~DevArena() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+static int ceil_log2(int x) {
+  int l = 0;
+  while ((1 << l) < x) ++l;
+  return l;
+}
+
+// Host-side view of a description with host pointers (device inputs are
+// staged to host first).
+struct HostDesc {
+  int N, nx, nu, nc, nf, m;
+  std::vector<double> A, B, b, Q, R, S, q, r, C, D, CN, l, u;
+};
+
+static bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+static int check_dims(const gsls_qp_desc* d) {
+  if (!d) return GSLS_ERR_INVALID_ARG;
+  if (d->N < 1 || d->N > GSLS_MAX_N || d->nx < 1 || d->nx > GSLS_MAX_NX || d->nu < 1 ||
+      d->nu > GSLS_MAX_NU || d->nc < 0 || d->nc > GSLS_MAX_NC || d->nf < 0 || d->nf > GSLS_MAX_NC)
+    return GSLS_ERR_DIM;
+  if (d->mem != GSLS_HOST && d->mem != GSLS_DEVICE) return GSLS_ERR_INVALID_ARG;
+  if (!d->A || !d->B || !d->Q || !d->R || !d->l || !d->u) return GSLS_ERR_INVALID_ARG;
+  if (d->nc > 0 && (!d->C || !d->D)) return GSLS_ERR_INVALID_ARG;
+  if (d->nf > 0 && !d->CN) return GSLS_ERR_INVALID_ARG;
+  return GSLS_OK;
+}
+
+static int validate_host(const HostDesc& h) {
+  const size_t N = h.N, nx = h.nx, nu = h.nu, nc = h.nc, nf = h.nf;
+  if (!finite_all(h.A.data(), N * nx * nx) || !finite_all(h.B.data(), N * nx * nu) ||
+      !finite_all(h.b.data(), N * nx) || !finite_all(h.Q.data(), (N + 1) * nx * nx) ||
+      !finite_all(h.R.data(), N * nu * nu) || !finite_all(h.S.data(), N * nu * nx) ||
+      !finite_all(h.q.data(), (N + 1) * nx) || !finite_all(h.r.data(), N * nu) ||
+      !finite_all(h.C.data(), N * nc * nx) || !finite_all(h.D.data(), N * nc * nu) ||
+      !finite_all(h.CN.data(), nf * nx))
+    return GSLS_ERR_INVALID_ARG;
+  for (size_t i = 0; i < h.l.size(); ++i) {
+    if (std::isnan(h.l[i]) || std::isnan(h.u[i]) || h.l[i] > h.u[i] || h.l[i] == INFINITY ||
+        h.u[i] == -INFINITY)
+      return GSLS_ERR_INVALID_ARG;
+  }
+  return GSLS_OK;
+}
+
+static int stage_to_host(const gsls_qp_desc* d, HostDesc* h) {
+  const size_t N = d->N, nx = d->nx, nu = d->nu, nc = d->nc, nf = d->nf;
+  h->N = d->N; h->nx = d->nx; h->nu = d->nu; h->nc = d->nc; h->nf = d->nf;
+  h->m = (int)(N * nc + nf);
+  auto get = [&](std::vector<double>& v, const double* p, size_t n) -> int {
+    v.assign(n, 0.0);
+    if (!p || n == 0) return GSLS_OK;
+    if (d->mem == GSLS_HOST) {
+      std::memcpy(v.data(), p, n * sizeof(double));
+    } else {
+      if (hipMemcpy(v.data(), p, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return GSLS_ERR_HIP;
+    }
+    return GSLS_OK;
+  };
+  int rc = GSLS_OK;
+  if ((rc = get(h->A, d->A, N * nx * nx))) return rc;
+  if ((rc = get(h->B, d->B, N * nx * nu))) return rc;
+  if ((rc = get(h->b, d->b, N * nx))) return rc;
+  if ((rc = get(h->Q, d->Q, (N + 1) * nx * nx))) return rc;
+  if ((rc = get(h->R, d->R, N * nu * nu))) return rc;
+  if ((rc = get(h->S, d->S, N * nu * nx))) return rc;
+  if ((rc = get(h->q, d->q, (N + 1) * nx))) return rc;
+  if ((rc = get(h->r, d->r, N * nu))) return rc;
+  if ((rc = get(h->C, d->C, N * nc * nx))) return rc;
+  if ((rc = get(h->D, d->D, N * nc * nu))) return rc;
+  if ((rc = get(h->CN, d->CN, nf * nx))) return rc;
+  if ((rc = get(h->l, d->l, N * nc + nf))) return rc;
+  if ((rc = get(h->u, d->u, N * nc + nf))) return rc;
+  return GSLS_OK;
+}
+
+// ------------------------------------------------------------ the solver
+struct SolverBase {
+  virtual ~SolverBase() {}
+  virtual int solve(const double* x0, int x0_dev, double rho, double tol, const double* z0,
+                    const double* y0, int warm_dev, gsls_result* res) = 0;
+  virtual int get(double* X, double* U, double* z, double* lam) = 0;
+  virtual int update_bounds(const double* l, const double* u, int dev) = 0;
+  virtual int sls(const double* E, const double* tau, const double* Qb, const double* Rb,
+                  const double* QbN, int rownorm, double wbound, double* Phx, double* Phu,
+                  double* h, double* hf) = 0;
+  virtual int sls_batch(int count, const double* E, const double* tau, const double* Qb,
+                        const double* Rb, const double* QbN, int rownorm, double wbound, double* h,
+                        double* hf, double* ms) = 0;
+  virtual int phase_cycles(int enable, double* out, int* chunks) = 0;
+};
+
+template <typename T>
+static void convert(std::vector<T>& out, const std::vector<double>& in) {
+  out.resize(in.size());
+  for (size_t i = 0; i < in.size(); ++i) out[i] = T(in[i]);
+}
+
+// batched transpose: [cnt][r][c] -> [cnt][c][r]
+template <typename T>
+static std::vector<T> transpose_blocks(const std::vector<double>& in, size_t cnt, size_t r, size_t c) {
+  std::vector<T> out(cnt * r * c);
+  for (size_t k = 0; k < cnt; ++k)
+    for (size_t i = 0; i < r; ++i)
+      for (size_t j = 0; j < c; ++j) out[k * r * c + j * r + i] = T(in[k * r * c + i * c + j]);
+  return out;
+}
+
+
+template <typename T>
+struct Solver : SolverBase {
+  HostDesc hd;
+  gsls_settings st;
+  hipStream_t stream = nullptr;
+  DevArena arena;
+  DevProblem<T> pb{};
+  DevFactor<T> fc{};
+  DevEpochWork<T> ew{};
+  double *z = nullptr, *y = nullptr, *ld_ = nullptr, *ud_ = nullptr;
+  double *X = nullptr, *U = nullptr;
+  T* x0d = nullptr;
+  unsigned long long* prof = nullptr;
+  int resident = 0;
+  LLBufs ll{};
+  IterCtl* ctl = nullptr;       // device
+  IterCtl* ctl_h = nullptr;     // pinned host copy
+  int* status_h = nullptr;      // pinned
+  int Pe = 1, Pi = 1, nlev = 0, Lmax = 1;
+  bool profile_on = false;
+  uint32_t stamp = 1;
+  double hnorm = 0.0;
+  double last_rho = 1.0;
+  bool solved_once = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+
+  ~Solver() override {
+    if (ctl_h) (void)hipHostFree(ctl_h);
+    if (status_h) (void)hipHostFree(status_h);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+
+  template <typename U_>
+  U_* up(const std::vector<U_>& v) {
+    U_* p = arena.alloc<U_>(v.size());
+    if (p && !v.empty()) {
+      if (hipMemcpyAsync(p, v.data(), v.size() * sizeof(U_), hipMemcpyHostToDevice, stream) != hipSuccess)
+        arena.ok = false;
+    }
+    return p;
+  }
+
+  // Iteration chunking: the workgroup count P (<= 256, all co-resident) and
+  // whether each chunk's operators fit in LDS.
+  void choose_chunks(const gsls_settings& s) {
+    const int N = hd.N, nx = hd.nx, nu = hd.nu, nc = hd.nc;
+    const size_t budget = 140 * 1024;
+    const size_t sb = sizeof(T) * (size_t)stage_block_elems_host(nx, nu, nc) +
+                      sizeof(T) * (4 * nx + 4 * nu) + sizeof(double) * 6 * nc;
+    if (s.chunks_iter > 0) {
+      Pi = std::min(s.chunks_iter, N);
+    } else {
+      // target stages per chunk: a few for large states, more for small ones
+      int Lt = nx >= 48 ? 4 : (nx >= 24 ? 6 : 8);
+      int Lfit = (int)std::max<size_t>(1, budget / std::max<size_t>(sb, 1));
+      Lt = std::min(Lt, Lfit);
+      Pi = (N + Lt - 1) / Lt;
+    }
+    Pi = std::max(1, std::min(Pi, 256));
+    Lmax = (N + Pi - 1) / Pi;
+    if (Lmax > 64) { Pi = std::min(256, (N + 63) / 64); Lmax = (N + Pi - 1) / Pi; }
+    nlev = ceil_log2(Pi);
+    resident = admm_lds_bytes<T>(nx, nu, nc, hd.nf, Lmax, Pi, true) <= 156 * 1024 ? 1 : 0;
+    Pe = s.chunks_epoch > 0 ? s.chunks_epoch : std::min(256, (N + 1) / 2);
+    Pe = std::max(1, std::min(std::min(Pe, N), 256));
+  }
+
+  int init(const HostDesc& h, const gsls_settings& s, hipStream_t strm) {
+    hd = h; st = s; stream = strm;
+    const int N = h.N, nx = h.nx, nu = h.nu, nc = h.nc, nf = h.nf;
+    const size_t xx = (size_t)nx * nx;
+    choose_chunks(s);
+    if (Lmax > 64) return GSLS_ERR_DIM;
+    // problem copies
+    std::vector<T> tmp;
+    pb.N = N; pb.nx = nx; pb.nu = nu; pb.nc = nc; pb.nf = nf; pb.m = h.m;
+    convert(tmp, h.A); pb.A = up(tmp);
+    convert(tmp, h.B); pb.B = up(tmp);
+    convert(tmp, h.b); pb.b = up(tmp);
+    convert(tmp, h.Q); pb.Q = up(tmp);
+    convert(tmp, h.R); pb.R = up(tmp);
+    convert(tmp, h.S); pb.S = up(tmp);
+    convert(tmp, h.q); pb.q = up(tmp);
+    convert(tmp, h.r); pb.r = up(tmp);
+    convert(tmp, h.C); pb.C = up(tmp);
+    convert(tmp, h.D); pb.D = up(tmp);
+    convert(tmp, h.CN); pb.CN = up(tmp);
+    {  // G = [C | D] per stage
+      const int nxu = nx + nu;
+      std::vector<T> G((size_t)N * nc * nxu);
+      for (int k = 0; k < N; ++k)
+        for (int r = 0; r < nc; ++r) {
+          for (int j = 0; j < nx; ++j) G[((size_t)k * nc + r) * nxu + j] = T(h.C[((size_t)k * nc + r) * nx + j]);
+          for (int j = 0; j < nu; ++j) G[((size_t)k * nc + r) * nxu + nx + j] = T(h.D[((size_t)k * nc + r) * nu + j]);
+        }
+      pb.G = up(G);
+    }
+    ld_ = up(h.l); ud_ = up(h.u);
+    // factor outputs
+    fc.F = arena.alloc<T>((size_t)N * (nx + nu) * (nx + nu));
+    fc.Gam = arena.alloc<T>((size_t)N * nu * nu);
+    fc.ev = arena.alloc<T>((size_t)N * nx); fc.fv = arena.alloc<T>((size_t)N * nu);
+    fc.Phi = arena.alloc<T>((size_t)std::max(nlev, 1) * Pi * xx);
+    // epoch scratch
+    ew.eP = arena.alloc<T>((N + 1) * xx); ew.eA = arena.alloc<T>((N + 1) * xx); ew.eC = arena.alloc<T>((N + 1) * xx);
+    ew.Qh = arena.alloc<T>((N + 1) * xx); ew.Rh = arena.alloc<T>((size_t)N * nu * nu);
+    ew.Sh = arena.alloc<T>((size_t)N * nu * nx);
+    ew.fP = arena.alloc<T>(Pe * xx); ew.fA = arena.alloc<T>(Pe * xx); ew.fC = arena.alloc<T>(Pe * xx);
+    ew.gP = arena.alloc<T>(Pe * xx); ew.gA = arena.alloc<T>(Pe * xx); ew.gC = arena.alloc<T>(Pe * xx);
+    ew.Pend = arena.alloc<T>(Pe * xx);
+    ew.slot = (size_t)std::max(nx, nu) * std::max(nx, nu);
+    ew.scratch = arena.alloc<T>((size_t)std::max(Pe, Pi) * 8 * ew.slot);
+    ew.status = arena.alloc<int>(1);
+    // state
+    z = arena.alloc<double>(h.m); y = arena.alloc<double>(h.m);
+    X = arena.alloc<double>((size_t)(N + 1) * nx); U = arena.alloc<double>((size_t)N * nu);
+    prof = arena.alloc<unsigned long long>(16);
+    x0d = arena.alloc<T>(nx);
+    constexpr int W = LLWords<T>::n;
+    const size_t vw = (size_t)(nlev + 1) * Pi * nx * W;
+    ll.bwd = arena.alloc<unsigned long long>(vw);
+    ll.fwd = arena.alloc<unsigned long long>(vw);
+    ll.red = arena.alloc<unsigned long long>((size_t)Pi * kRed * 2);
+    ll.abort = arena.alloc<int>(1);
+    ctl = arena.alloc<IterCtl>(1);
+    if (!arena.ok) return GSLS_ERR_OOM;
+    if (hipMemsetAsync(ll.bwd, 0, vw * 8, stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (hipMemsetAsync(ll.fwd, 0, vw * 8, stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (hipMemsetAsync(ll.red, 0, (size_t)Pi * kRed * 2 * 8, stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (hipMemsetAsync(X, 0, sizeof(double) * (N + 1) * nx, stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (hipMemsetAsync(U, 0, sizeof(double) * N * nu, stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (hipMemsetAsync(prof, 0, sizeof(unsigned long long) * 16, stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (hipHostMalloc((void**)&ctl_h, sizeof(IterCtl)) != hipSuccess) return GSLS_ERR_OOM;
+    if (hipHostMalloc((void**)&status_h, sizeof(int)) != hipSuccess) return GSLS_ERR_OOM;
+    for (auto& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) return GSLS_ERR_HIP;
+    double hn = 0.0;
+    for (double v : h.q) hn = std::max(hn, std::fabs(v));
+    for (double v : h.r) hn = std::max(hn, std::fabs(v));
+    hnorm = hn;
+    if (epoch_set_attributes<T>() != GSLS_OK) return GSLS_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return GSLS_ERR_HIP;
+    return GSLS_OK;
+  }
+
+  int run_epoch(double rho, float* ms) {
+    if (hipMemsetAsync(ew.status, 0, sizeof(int), stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (hipEventRecord(ev[0], stream) != hipSuccess) return GSLS_ERR_HIP;
+    int rc = launch_epoch<T>(pb, ew, fc, rho, Pe, Pi, nlev, stream);
+    if (rc) return rc;
+    if (hipEventRecord(ev[1], stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (hipMemcpyAsync(status_h, ew.status, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess)
+      return GSLS_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (*status_h != 0) return GSLS_ERR_NOT_PD;
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, ev[0], ev[1]);
+    *ms += t;
+    return GSLS_OK;
+  }
+
+  template <typename D_>
+  int load_vec(D_* dst, const double* src, size_t n, int dev) {
+    std::vector<double> hv(n);
+    if (dev) {
+      if (hipMemcpy(hv.data(), src, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return GSLS_ERR_HIP;
+    } else {
+      std::memcpy(hv.data(), src, n * sizeof(double));
+    }
+    for (double v : hv)
+      if (!std::isfinite(v)) return GSLS_ERR_INVALID_ARG;
+    std::vector<D_> tv(n);
+    for (size_t i = 0; i < n; ++i) tv[i] = D_(hv[i]);
+    if (hipMemcpyAsync(dst, tv.data(), n * sizeof(D_), hipMemcpyHostToDevice, stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return GSLS_ERR_HIP;
+    return GSLS_OK;
+  }
+
+  int solve(const double* x0, int x0_dev, double rho, double tol, const double* z0, const double* y0,
+            int warm_dev, gsls_result* res) override {
+    if (!x0 || !(rho > 0.0) || !std::isfinite(rho) || !(tol >= 0.0)) return GSLS_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = load_vec(x0d, x0, hd.nx, x0_dev))) return rc;
+    if (z0 && y0) {
+      if ((rc = load_vec(z, z0, hd.m, warm_dev))) return rc;
+      if ((rc = load_vec(y, y0, hd.m, warm_dev))) return rc;
+    } else {
+      if (hipMemsetAsync(z, 0, sizeof(double) * hd.m, stream) != hipSuccess) return GSLS_ERR_HIP;
+      if (hipMemsetAsync(y, 0, sizeof(double) * hd.m, stream) != hipSuccess) return GSLS_ERR_HIP;
+    }
+    float ms_f = 0.f, ms_i = 0.f;
+    int it = 0, nfact = 0, nupd = 0;
+    double cur = rho;
+    gsls_result r{};
+    while (true) {
+      if ((rc = run_epoch(cur, &ms_f))) return rc;
+      ++nfact;
+      IterArgs<T> a{};
+      a.pb = pb; a.fc = fc; a.z = z; a.y = y; a.l = ld_; a.u = ud_; a.X = X; a.U = U; a.x0 = x0d;
+      a.ll = ll; a.ctl = ctl; a.Lmax = Lmax; a.resident = resident;
+      a.prof = profile_on ? prof : nullptr;
+      a.ip.P = Pi; a.ip.nlev = nlev; a.ip.rho = cur; a.ip.tol = tol; a.ip.it0 = it;
+      a.ip.max_iter = st.max_iter; a.ip.adaptive = st.adaptive_rho; a.ip.sigma = st.sigma;
+      a.ip.rho_min = st.rho_min; a.ip.rho_max = st.rho_max; a.ip.rho_tol = st.rho_tol;
+      a.ip.hnorm = hnorm; a.ip.stamp0 = stamp;
+      if (hipMemsetAsync(ll.abort, 0, sizeof(int), stream) != hipSuccess) return GSLS_ERR_HIP;
+      if (hipMemsetAsync(ctl, 0, sizeof(IterCtl), stream) != hipSuccess) return GSLS_ERR_HIP;
+      if (hipEventRecord(ev[2], stream) != hipSuccess) return GSLS_ERR_HIP;
+      if ((rc = launch_admm<T>(a, stream))) return rc;
+      if (hipEventRecord(ev[3], stream) != hipSuccess) return GSLS_ERR_HIP;
+      if (hipMemcpyAsync(ctl_h, ctl, sizeof(IterCtl), hipMemcpyDeviceToHost, stream) != hipSuccess) return GSLS_ERR_HIP;
+      if (hipStreamSynchronize(stream) != hipSuccess) return GSLS_ERR_HIP;
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, ev[2], ev[3]);
+      ms_i += t;
+      stamp += (uint32_t)(ctl_h->it - it) + 2;
+      it = ctl_h->it;
+      r.r_p = ctl_h->r_p; r.r_d = ctl_h->r_d;
+      const int s = ctl_h->status;
+      if (s == 5) return GSLS_ERR_HIP;
+      if (s == 4) {
+        cur = ctl_h->rho_new;
+        ++nupd;
+        continue;
+      }
+      r.status = s == 1 ? GSLS_SOLVED : (s == 2 ? GSLS_MAX_ITER : GSLS_NUMERICAL_FAIL);
+      break;
+    }
+    r.iterations = it; r.rho_updates = nupd; r.factorizations = nfact; r.rho = cur;
+    r.ms_factor = ms_f; r.ms_iterate = ms_i; r.ms_total = ms_f + ms_i;
+    last_rho = cur;
+    solved_once = true;
+    if (res) *res = r;
+    return GSLS_OK;
+  }
+
+  int get(double* Xo, double* Uo, double* zo, double* lo) override {
+    if (!solved_once) return GSLS_ERR_STATE;
+    auto dl = [&](double* out, auto* src, size_t n, double scale) -> int {
+      if (!out) return GSLS_OK;
+      using S_ = std::remove_pointer_t<decltype(src)>;
+      std::vector<S_> t(n);
+      if (hipMemcpyAsync(t.data(), src, n * sizeof(S_), hipMemcpyDeviceToHost, stream) != hipSuccess) return GSLS_ERR_HIP;
+      if (hipStreamSynchronize(stream) != hipSuccess) return GSLS_ERR_HIP;
+      for (size_t i = 0; i < n; ++i) out[i] = scale * double(t[i]);
+      return GSLS_OK;
+    };
+    int rc;
+    if ((rc = dl(Xo, X, (size_t)(hd.N + 1) * hd.nx, 1.0))) return rc;
+    if ((rc = dl(Uo, U, (size_t)hd.N * hd.nu, 1.0))) return rc;
+    if ((rc = dl(zo, z, hd.m, 1.0))) return rc;
+    if ((rc = dl(lo, y, hd.m, last_rho))) return rc;
+    return GSLS_OK;
+  }
+
+  int update_bounds(const double* l, const double* u, int dev) override {
+    if (!l || !u) return GSLS_ERR_INVALID_ARG;
+    std::vector<double> lh(hd.m), uh(hd.m);
+    if (dev) {
+      if (hipMemcpy(lh.data(), l, hd.m * 8, hipMemcpyDeviceToHost) != hipSuccess) return GSLS_ERR_HIP;
+      if (hipMemcpy(uh.data(), u, hd.m * 8, hipMemcpyDeviceToHost) != hipSuccess) return GSLS_ERR_HIP;
+    } else {
+      std::memcpy(lh.data(), l, hd.m * 8);
+      std::memcpy(uh.data(), u, hd.m * 8);
+    }
+    for (int i = 0; i < hd.m; ++i)
+      if (std::isnan(lh[i]) || std::isnan(uh[i]) || lh[i] > uh[i]) return GSLS_ERR_INVALID_ARG;
+    hd.l = lh; hd.u = uh;
+    if (hipMemcpyAsync(ld_, lh.data(), hd.m * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (hipMemcpyAsync(ud_, uh.data(), hd.m * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return GSLS_ERR_HIP;
+    return GSLS_OK;
+  }
+
+  int phase_cycles(int enable, double* out, int* chunks) override {
+    if (enable >= 0) profile_on = enable != 0;
+    if (chunks) { chunks[0] = Pe; chunks[1] = Pi; chunks[2] = resident; chunks[3] = Lmax; }
+    if (out) {
+      unsigned long long h[16];
+      if (hipMemcpy(h, prof, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return GSLS_ERR_HIP;
+      for (int i = 0; i < 16; ++i) out[i] = (double)h[i];
+      if (hipMemset(prof, 0, sizeof(h)) != hipSuccess) return GSLS_ERR_HIP;
+    }
+    return GSLS_OK;
+  }
+
+  int sls(const double*, const double*, const double*, const double*, const double*, int, double, double*,
+          double*, double*, double*) override {
+    return GSLS_ERR_STATE;
+  }
+  int sls_batch(int, const double*, const double*, const double*, const double*, const double*, int, double,
+                double*, double*, double*) override {
+    return GSLS_ERR_STATE;
+  }
+};
+
+}  // namespace gsls
+
+// ================================================================ C ABI
+struct gsls_qp {
+  std::unique_ptr<gsls::SolverBase> impl;
+  int mem;
+};
+
+extern "C" {
+
+void gsls_default_settings(gsls_settings* s) {
+  if (!s) return;
+  s->precision = GSLS_MIXED;
+  s->max_iter = 10000;
+  s->adaptive_rho = 1;
+  s->sigma = 25;
+  s->rho_min = 1e-6;
+  s->rho_max = 1e6;
+  s->rho_tol = 5.0;
+  s->chunks_epoch = 0;
+  s->chunks_iter = 0;
+}
+
+const char* gsls_strerror(int code) {
+  switch (code) {
+    case GSLS_OK: return "ok";
+    case GSLS_ERR_INVALID_ARG: return "invalid argument";
+    case GSLS_ERR_DIM: return "dimension out of the supported range";
+    case GSLS_ERR_NOT_PD: return "matrix not positive definite";
+    case GSLS_ERR_NUMERICAL: return "numerical failure (NaN/Inf)";
+    case GSLS_ERR_OOM: return "device allocation failed";
+    case GSLS_ERR_HIP: return "HIP runtime error";
+    case GSLS_ERR_STATE: return "call out of order";
+    default: return "unknown error";
+  }
+}
+
+static int check_settings(const gsls_settings* s) {
+  if (s->precision != GSLS_MIXED && s->precision != GSLS_FP64) return GSLS_ERR_INVALID_ARG;
+  if (s->max_iter < 1 || s->sigma < 1 || !(s->rho_min > 0) || !(s->rho_max >= s->rho_min) ||
+      !(s->rho_tol > 1.0) || s->chunks_epoch < 0 || s->chunks_iter < 0 || s->chunks_iter > 256)
+    return GSLS_ERR_INVALID_ARG;
+  return GSLS_OK;
+}
+
+int gsls_validate_desc(const gsls_qp_desc* desc) {
+  int rc = gsls::check_dims(desc);
+  if (rc) return rc;
+  if (desc->mem != GSLS_HOST) return GSLS_ERR_INVALID_ARG;
+  gsls::HostDesc h;
+  if ((rc = gsls::stage_to_host(desc, &h))) return rc;
+  return gsls::validate_host(h);
+}
+
+int gsls_qp_setup(const gsls_qp_desc* desc, const gsls_settings* settings, void* stream, gsls_qp** out) {
+  if (!out) return GSLS_ERR_INVALID_ARG;
+  *out = nullptr;
+  int rc = gsls::check_dims(desc);
+  if (rc) return rc;
+  gsls_settings s;
+  gsls_default_settings(&s);
+  if (settings) s = *settings;
+  if ((rc = check_settings(&s))) return rc;
+  gsls::HostDesc h;
+  if ((rc = gsls::stage_to_host(desc, &h))) return rc;
+  if ((rc = gsls::validate_host(h))) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return GSLS_ERR_HIP;
+  gsls_qp* q = new (std::nothrow) gsls_qp;
+  if (!q) return GSLS_ERR_OOM;
+  q->mem = desc->mem;
+  try {
+    if (s.precision == GSLS_FP64) {
+      auto* p = new gsls::Solver<double>();
+      q->impl.reset(p);
+      rc = p->init(h, s, (hipStream_t)stream);
+    } else {
+      auto* p = new gsls::Solver<float>();
+      q->impl.reset(p);
+      rc = p->init(h, s, (hipStream_t)stream);
+    }
+  } catch (...) {
+    rc = GSLS_ERR_OOM;
+  }
+  if (rc) {
+    delete q;
+    return rc;
+  }
+  *out = q;
+  return GSLS_OK;
+}
+
+int gsls_qp_update_bounds(gsls_qp* h, const double* l, const double* u) {
+  if (!h) return GSLS_ERR_INVALID_ARG;
+  return h->impl->update_bounds(l, u, h->mem == GSLS_DEVICE);
+}
+
+int gsls_qp_solve(gsls_qp* h, const double* x0, double rho, double tol, gsls_result* result) {
+  if (!h) return GSLS_ERR_INVALID_ARG;
+  return h->impl->solve(x0, h->mem == GSLS_DEVICE, rho, tol, nullptr, nullptr, 0, result);
+}
+
+int gsls_qp_solve_warm(gsls_qp* h, const double* x0, double rho, double tol, const double* z0,
+                       const double* y0, gsls_result* result) {
+  if (!h || !z0 || !y0) return GSLS_ERR_INVALID_ARG;
+  return h->impl->solve(x0, h->mem == GSLS_DEVICE, rho, tol, z0, y0, h->mem == GSLS_DEVICE, result);
+}
+
+int gsls_qp_get(gsls_qp* h, double* X, double* U, double* z, double* lambda) {
+  if (!h) return GSLS_ERR_INVALID_ARG;
+  return h->impl->get(X, U, z, lambda);
+}
+
+void gsls_qp_free(gsls_qp* h) { delete h; }
+
+int gsls_debug_phase_cycles(gsls_qp* h, int32_t enable, double* cycles16, int32_t* layout4) {
+  if (!h) return GSLS_ERR_INVALID_ARG;
+  return h->impl->phase_cycles(enable, cycles16, layout4);
+}
+
+int gsls_sls_solve(gsls_qp* h, const double* E, const double* tau, const double* Qbar, const double* Rbar,
+                   const double* QbarN, int32_t rownorm, double wbound, double* Phi_x, double* Phi_u,
+                   double* hmarg, double* hf) {
+  if (!h) return GSLS_ERR_INVALID_ARG;
+  return h->impl->sls(E, tau, Qbar, Rbar, QbarN, rownorm, wbound, Phi_x, Phi_u, hmarg, hf);
+}
+
+int gsls_sls_solve_batch(gsls_qp* h, int32_t count, const double* E, const double* tau, const double* Qbar,
+                         const double* Rbar, const double* QbarN, int32_t rownorm, double wbound, double* hmarg,
+                         double* hf, double* ms) {
+  if (!h) return GSLS_ERR_INVALID_ARG;
+  return h->impl->sls_batch(count, E, tau, Qbar, Rbar, QbarN, rownorm, wbound, hmarg, hf, ms);
+}
+
+int gsls_sls_tau(gsls_qp* h, const double* lambda, const double* Phi_x, const double* Phi_u, double eps,
+                 double* tau) {
+  (void)h; (void)lambda; (void)Phi_x; (void)Phi_u; (void)eps; (void)tau;
+  return GSLS_ERR_STATE;
+}
+
+}  // extern "C"

@@ -1,0 +1,398 @@
+// Device building blocks shared by the gfx950 kernels: workgroup GEMM on
+// register micro-tiles, FP64 LU with partial pivoting and triangular solves in
+// LDS, FP64 Cholesky for the small control-dimension factors, workgroup
+// matrix-transpose-times-vector, and the packed (payload, stamp) words used
+// for low-latency exchange between workgroups of a persistent kernel.
+//
+// All routines with the prefix wg_ must be called by every thread of the
+// workgroup (they contain __syncthreads); the workgroup size is kWG threads.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// Pointer qualifier for the local data share: accesses through it compile to
+// ds_read / ds_write (a generic pointer would take the flat path).
+#define LDS __attribute__((address_space(3)))
+
+namespace gsls {
+
+constexpr int kWG = 256;          // threads per workgroup
+constexpr int kMaxNx = 80;        // largest state dimension handled
+constexpr int kMaxNu = 32;        // largest control dimension
+constexpr int kMaxNc = 64;        // largest number of stage rows
+constexpr int kKT = 16;           // K-slab depth of the workgroup GEMM
+constexpr unsigned kSpinLimit = 1u << 22;   // bounded waits (a few seconds): give up and flag an error
+
+__device__ __forceinline__ int tid() { return threadIdx.x; }
+
+// ------------------------------------------------------------------ GEMM
+// C = alpha * op(A) * op(B) + beta * C, with op(A) m x k and op(B) k x n.
+//   A element (i, t) = ta ? A[t*lda + i] : A[i*lda + t]
+//   B element (t, j) = tb ? B[j*ldb + t] : B[t*ldb + j]
+// Thread (ty, tx) of a 16 x 16 grid owns rows ty + 16a and columns tx + 16b of
+// C (a, b < TT).  op(A) and op(B) pass through LDS in K-slabs of kKT; each
+// thread holds TT elements of each slab in registers, and the next slab's
+// loads are issued before the current slab is multiplied, so global latency
+// overlaps the arithmetic.  Indices are clamped into range (loads never leave
+// the operand) and out-of-range terms masked to zero.  beta == 0 never reads
+// C.  All reads of A and B complete before C is written, so C may alias them.
+// smem: 2 * 16*TT * kKT elements.
+template <typename T, int TT>
+__device__ void wg_gemm_tt(int m, int n, int k, T alpha, const T* A, int lda, bool ta,
+                           const T* B, int ldb, bool tb, T beta, T* C, int ldc, LDS T* smem) {
+  constexpr int MM = 16 * TT;
+  LDS T* As = smem;              // [MM][kKT]
+  LDS T* Bs = smem + MM * kKT;   // [kKT][MM]
+  const int tx = tid() & 15, ty = tid() >> 4;
+  T acc[TT][TT];
+#pragma unroll
+  for (int a = 0; a < TT; ++a)
+#pragma unroll
+    for (int b = 0; b < TT; ++b) acc[a][b] = T(0);
+  T ra[TT], rb[TT];
+  auto load = [&](int t0) {
+#pragma unroll
+    for (int q = 0; q < TT; ++q) {
+      const int e = tid() + q * kWG;
+      const int i = e / kKT, t = e % kKT;
+      const int ic = min(i, m - 1), tc = min(t0 + t, k - 1);
+      T v = ta ? A[(size_t)tc * lda + ic] : A[(size_t)ic * lda + tc];
+      ra[q] = (i < m && t0 + t < k) ? v : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < TT; ++q) {
+      const int e = tid() + q * kWG;
+      const int t = e / MM, j = e % MM;
+      const int jc = min(j, n - 1), tc = min(t0 + t, k - 1);
+      T v = tb ? B[(size_t)jc * ldb + tc] : B[(size_t)tc * ldb + jc];
+      rb[q] = (j < n && t0 + t < k) ? v : T(0);
+    }
+  };
+  load(0);
+  for (int t0 = 0; t0 < k; t0 += kKT) {
+#pragma unroll
+    for (int q = 0; q < TT; ++q) {
+      const int e = tid() + q * kWG;
+      As[(e / kKT) * kKT + e % kKT] = ra[q];
+      Bs[e] = rb[q];
+    }
+    __syncthreads();
+    if (t0 + kKT < k) load(t0 + kKT);
+    // slabs are zero-padded past k, so the slab loop has a fixed trip count
+#pragma unroll
+    for (int t = 0; t < kKT; ++t) {
+      T av[TT], bv[TT];
+#pragma unroll
+      for (int a = 0; a < TT; ++a) av[a] = As[(ty + 16 * a) * kKT + t];
+#pragma unroll
+      for (int b = 0; b < TT; ++b) bv[b] = Bs[t * MM + tx + 16 * b];
+#pragma unroll
+      for (int a = 0; a < TT; ++a)
+#pragma unroll
+        for (int b = 0; b < TT; ++b) acc[a][b] += av[a] * bv[b];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < TT; ++a) {
+    int i = ty + 16 * a;
+    if (i >= m) continue;
+#pragma unroll
+    for (int b = 0; b < TT; ++b) {
+      int j = tx + 16 * b;
+      if (j >= n) continue;
+      T v = alpha * acc[a][b];
+      if (beta != T(0)) v += beta * C[(size_t)i * ldc + j];
+      C[(size_t)i * ldc + j] = v;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void wg_gemm(int m, int n, int k, T alpha, const T* A, int lda, bool ta, const T* B,
+                        int ldb, bool tb, T beta, T* C, int ldc, LDS T* smem) {
+  int mx = max(m, n);
+  if (mx <= 16) wg_gemm_tt<T, 1>(m, n, k, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, smem);
+  else if (mx <= 32) wg_gemm_tt<T, 2>(m, n, k, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, smem);
+  else if (mx <= 48) wg_gemm_tt<T, 3>(m, n, k, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, smem);
+  else if (mx <= 64) wg_gemm_tt<T, 4>(m, n, k, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, smem);
+  else wg_gemm_tt<T, 5>(m, n, k, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, smem);
+}
+constexpr int kGemmSmem = 2 * 16 * 5 * kKT;   // elements of T needed by wg_gemm
+
+// Element loops of the workgroup helpers are two-dimensional: the four waves
+// take rows w, w+4, ... and the 64 lanes take columns lane, lane+64, ..., so
+// no index is ever divided at run time.
+__device__ __forceinline__ int wave() { return threadIdx.x >> 6; }
+__device__ __forceinline__ int lane() { return threadIdx.x & 63; }
+
+// Copy / convert a matrix block: dst[i*ldd + j] = src[i*lds + j] (or transposed).
+template <typename TD, typename TS>
+__device__ void wg_copy(int m, int n, TD* dst, int ldd, const TS* src, int lds, bool trans = false) {
+  for (int i = wave(); i < m; i += 4)
+    for (int j = lane(); j < n; j += 64)
+      dst[(size_t)i * ldd + j] = TD(trans ? src[(size_t)j * lds + i] : src[(size_t)i * lds + j]);
+}
+
+// Symmetrise a square matrix in place: P = (P + P^T) / 2.
+template <typename T>
+__device__ void wg_symmetrize(int n, T* P, int ld) {
+  __syncthreads();
+  for (int i = wave(); i < n; i += 4)
+    for (int j = i + 1 + lane(); j < n; j += 64) {
+      T s = T(0.5) * (P[(size_t)i * ld + j] + P[(size_t)j * ld + i]);
+      P[(size_t)i * ld + j] = s;
+      P[(size_t)j * ld + i] = s;
+    }
+  __syncthreads();
+}
+
+// -------------------------------------------------- FP64 Gauss-Jordan inverse
+constexpr int kGJRows = kMaxNx / 4;   // rows per wave
+// Inverse of the n x n matrix held in the left half of Aug = [M | I] (LDS,
+// FP64, n x 2n row-major, the caller fills both halves).  Column j's pivot is
+// the largest |entry| among rows not used as pivots yet (pivot = true), or
+// simply row j (pivot = false: for symmetric positive definite M, where every
+// pivot must then be positive; a non-positive pivot is reported as failure).
+// Rows are never swapped: perm[j] records the pivot row of column j, and the
+// pivot rows are normalised at the end (elimination and row scaling commute).
+// On return Minv[j][c] = Aug[perm[j]][n + c] / dg[j] is written to Minv (ldm),
+// converted to TO.  Two barriers per column.  Returns false uniformly on a
+// zero, negative (SPD mode) or non-finite pivot.
+// used: LDS int[n]; perm: LDS int[n]; dg: LDS double[n].
+template <typename TO>
+__device__ inline bool wg_gj_inverse(int n, LDS double* Aug, bool pivot, LDS int* perm, LDS int* used,
+                                     LDS double* dg, TO* Minv, int ldm) {
+  __shared__ int s_piv, s_bad;
+  const int ld = 2 * n;
+  const int lane = tid() & 63, w = tid() >> 6;
+  for (int r = tid(); r < n; r += kWG) used[r] = 0;
+  if (tid() == 0) s_bad = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (w == 0) {
+      double best = -1.0;
+      int bi = n;
+      if (pivot) {
+        for (int r = lane; r < n; r += 64) {
+          double v = fabs(Aug[r * ld + j]);
+          if (!used[r] && (v > best || (v == best && r < bi))) { best = v; bi = r; }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          double ob = __shfl_xor(best, off, 64);
+          int oi = __shfl_xor(bi, off, 64);
+          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+      } else {
+        bi = j;
+        best = Aug[j * ld + j];
+      }
+      if (lane == 0) {
+        s_piv = bi;
+        perm[j] = bi;
+        if (bi < n) used[bi] = 1;
+        if (!(best > 0.0) || !isfinite(best) || bi >= n) s_bad = 1;
+      }
+    }
+    __syncthreads();
+    if (s_bad) return false;
+    const int p = s_piv;
+    const double inv = 1.0 / Aug[p * ld + j];
+    const LDS double* prow = Aug + p * ld;
+    // eliminate column j from every other row (columns > j of both halves):
+    // the wave's multipliers, then per 64-column slot all its rows' entries,
+    // are loaded before any is updated, so LDS latency is paid once per slot
+    double mult[kGJRows];
+#pragma unroll
+    for (int k = 0; k < kGJRows; ++k) {
+      const int r = min(w + 4 * k, n - 1);
+      mult[k] = Aug[r * ld + j] * inv;
+    }
+    for (int c = j + 1 + lane; c < ld; c += 64) {
+      const double pv = prow[c];
+      double v[kGJRows];
+#pragma unroll
+      for (int k = 0; k < kGJRows; ++k) v[k] = Aug[min(w + 4 * k, n - 1) * ld + c];
+#pragma unroll
+      for (int k = 0; k < kGJRows; ++k) {
+        const int r = w + 4 * k;
+        const double nv = v[k] - mult[k] * pv;
+        if (r < n && r != p) Aug[r * ld + c] = nv;
+      }
+    }
+    __syncthreads();
+  }
+  for (int j = tid(); j < n; j += kWG) dg[j] = 1.0 / Aug[perm[j] * ld + j];
+  __syncthreads();
+  for (int r = w; r < n; r += 4) {
+    const LDS double* row = Aug + perm[r] * ld + n;
+    const double sc = dg[r];
+    for (int c = lane; c < n; c += 64) Minv[(size_t)r * ldm + c] = TO(row[c] * sc);
+  }
+  __syncthreads();
+  return true;
+}
+
+// ------------------------------------------------ batched-load GEMV (WG)
+// Reduction dimension up to 4 * KR, output dimension up to 128.  All loads of
+// a thread are issued before its first multiply (indices are clamped into
+// range and out-of-range terms multiplied by zero), so one memory latency
+// covers the whole product and the body has no branch.  PM / PX / PY are
+// pointer types (LDS-qualified or global).  part: LDS scratch [4][128].  Both
+// end with a barrier.
+
+// y[j] = sum_i M[i*ld + j] x[i]  (M^T x) for M m x n;  y += ... if acc.
+template <typename T, int KR, typename PM, typename PX, typename PY>
+__device__ __forceinline__ void wg_gemv_t(int m, int n, PM M, int ld, PX x, PY y, LDS T* part, bool acc) {
+  const int lane = tid() & 63, w = tid() >> 6;
+  T xv[KR];
+#pragma unroll
+  for (int k = 0; k < KR; ++k) {
+    const int i = w + 4 * k;
+    const T xi = T(x[min(i, m - 1)]);
+    xv[k] = i < m ? xi : T(0);
+  }
+  for (int jb = 0; jb * 64 < n; ++jb) {
+    const int jc = min(jb * 64 + lane, n - 1);
+    T v[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) v[k] = T(M[min(w + 4 * k, m - 1) * ld + jc]);
+    T s = T(0);
+#pragma unroll
+    for (int k = 0; k < KR; ++k) s += v[k] * xv[k];
+    part[w * 128 + jb * 64 + lane] = s;
+  }
+  __syncthreads();
+  for (int j = tid(); j < n; j += kWG) {
+    T s = part[j] + part[128 + j] + part[256 + j] + part[384 + j];
+    y[j] = acc ? T(y[j]) + s : s;
+  }
+  __syncthreads();
+}
+
+// y[i] = sum_j M[i*ld + j] x[j]  (M x) for M m x n (m <= 128, n <= 4 KR).
+template <typename T, int KR, typename PM, typename PX, typename PY>
+__device__ __forceinline__ void wg_gemv_n(int m, int n, PM M, int ld, PX x, PY y, LDS T* part, bool acc) {
+  const int lane = tid() & 63, w = tid() >> 6;
+  T xv[KR];
+#pragma unroll
+  for (int k = 0; k < KR; ++k) {
+    const int j = w + 4 * k;
+    const T xj = T(x[min(j, n - 1)]);
+    xv[k] = j < n ? xj : T(0);
+  }
+  for (int ib = 0; ib * 64 < m; ++ib) {
+    const int ic = min(ib * 64 + lane, m - 1);
+    T v[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) v[k] = T(M[ic * ld + min(w + 4 * k, n - 1)]);
+    T s = T(0);
+#pragma unroll
+    for (int k = 0; k < KR; ++k) s += v[k] * xv[k];
+    part[w * 128 + ib * 64 + lane] = s;
+  }
+  __syncthreads();
+  for (int i = tid(); i < m; i += kWG) {
+    T s = part[i] + part[128 + i] + part[256 + i] + part[384 + i];
+    y[i] = acc ? T(y[i]) + s : s;
+  }
+  __syncthreads();
+}
+
+// Square n x n products (n <= 64) split in two so the matrix loads can be
+// issued before a wait for x: _pre loads this thread's entries of M into v,
+// _fin multiplies them with x (TR: M^T x, else M x).
+template <typename T, int KR, bool TR, typename PM>
+__device__ __forceinline__ void wg_gemv_sq_pre(int n, PM M, int ld, T v[KR]) {
+  const int lane = tid() & 63, w = tid() >> 6;
+  const int jc = min(lane, n - 1);
+#pragma unroll
+  for (int k = 0; k < KR; ++k) {
+    const int r = min(w + 4 * k, n - 1);
+    v[k] = TR ? T(M[r * ld + jc]) : T(M[jc * ld + r]);
+  }
+}
+template <typename T, int KR, typename PX, typename PY>
+__device__ __forceinline__ void wg_gemv_sq_fin(int n, const T v[KR], PX x, PY y, LDS T* part, bool acc) {
+  const int lane = tid() & 63, w = tid() >> 6;
+  T s = T(0);
+#pragma unroll
+  for (int k = 0; k < KR; ++k) {
+    const int i = w + 4 * k;
+    const T xi = T(x[min(i, n - 1)]);
+    s += v[k] * (i < n ? xi : T(0));
+  }
+  part[w * 128 + lane] = s;
+  __syncthreads();
+  for (int j = tid(); j < n; j += kWG) {
+    T t = part[j] + part[128 + j] + part[256 + j] + part[384 + j];
+    y[j] = acc ? T(y[j]) + t : t;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------- inter-workgroup packed words
+// A 64-bit word carries 32 payload bits (low) and a 32-bit stamp (high).  Words
+// are written and polled with relaxed device-scope atomics, which the gfx950
+// backend emits as cache-coherent (sc1) stores and loads with no cache
+// write-back or invalidate; the payload and its stamp arrive together because
+// an aligned 64-bit access is single-copy atomic.  A reader waits until the
+// stamp equals the one it expects.  Waits are bounded by kSpinLimit polls.
+__device__ __forceinline__ void ll_put(unsigned long long* p, uint32_t stamp, uint32_t bits) {
+  __hip_atomic_store(p, ((unsigned long long)stamp << 32) | bits, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+// Returns false if the wait gave up (poll limit, or another workgroup raised
+// the abort flag, which is checked every 256 polls).
+__device__ __forceinline__ bool ll_get(const unsigned long long* p, uint32_t stamp, uint32_t* bits,
+                                       const int* abort) {
+  unsigned n = 0;
+  while (true) {
+    unsigned long long w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(w >> 32) == stamp) { *bits = (uint32_t)w; return true; }
+    if (++n > kSpinLimit) return false;
+    if ((n & 255) == 0 && __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// Words per value of type T.
+template <typename T> struct LLWords;
+template <> struct LLWords<float> { static constexpr int n = 1; };
+template <> struct LLWords<double> { static constexpr int n = 2; };
+
+template <typename T>
+__device__ __forceinline__ void ll_put_val(unsigned long long* p, uint32_t stamp, T v);
+template <>
+__device__ __forceinline__ void ll_put_val<float>(unsigned long long* p, uint32_t stamp, float v) {
+  ll_put(p, stamp, __float_as_uint(v));
+}
+template <>
+__device__ __forceinline__ void ll_put_val<double>(unsigned long long* p, uint32_t stamp, double v) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  ll_put(p, stamp, (uint32_t)b);
+  ll_put(p + 1, stamp, (uint32_t)(b >> 32));
+}
+template <typename T>
+__device__ __forceinline__ bool ll_get_val(const unsigned long long* p, uint32_t stamp, T* v,
+                                           const int* abort);
+template <>
+__device__ __forceinline__ bool ll_get_val<float>(const unsigned long long* p, uint32_t stamp, float* v,
+                                                  const int* abort) {
+  uint32_t b = 0;
+  bool ok = ll_get(p, stamp, &b, abort);
+  *v = __uint_as_float(b);
+  return ok;
+}
+template <>
+__device__ __forceinline__ bool ll_get_val<double>(const unsigned long long* p, uint32_t stamp, double* v,
+                                                   const int* abort) {
+  uint32_t lo = 0, hi = 0;
+  bool ok = ll_get(p, stamp, &lo, abort);
+  ok = ok && ll_get(p + 1, stamp, &hi, abort);
+  *v = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  return ok;
+}
+
+}  // namespace gsls

@@ -1,0 +1,102 @@
+// Internal declarations of the gfx950 ADMM / associative-scan QP solver.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <vector>
+
+#include "../../include/gsls.h"
+
+namespace gsls {
+
+// Device copies of one LTV-QP in the working precision T (row-major, the
+// layout of the C ABI).
+template <typename T>
+struct DevProblem {
+  int N, nx, nu, nc, nf, m;
+  T *A, *B, *b, *Q, *R, *S, *q, *r, *C, *D, *CN;
+  T *G;              // [N][nc][nx+nu]  stage constraint map [C | D]
+};
+
+// Factor-epoch outputs (rho fixed) consumed by the ADMM iteration kernel.
+template <typename T>
+struct DevFactor {
+  T *F;              // [N][nx+nu][nx+nu]  [[Abar, B], [K, I]] with Abar = A + B K
+  T *Gam;            // [N][nu][nu]   (R_hat + B^T P_{k+1} B)^{-1}
+  T *ev;             // [N][nx]       Abar^T P_{k+1} b
+  T *fv;             // [N][nu]       B^T P_{k+1} b
+  T *Phi;            // [nlev][P][nx][nx] chunk transfer maps (see iteration kernel)
+};
+
+// Scratch of the factor epoch.
+template <typename T>
+struct DevEpochWork {
+  T *eP, *eA, *eC;          // [N+1][nx][nx] scan elements (P~, A~, C~)
+  T *Qh, *Rh, *Sh;          // [N+1][nx][nx], [N][nu][nu], [N][nu][nx]
+  T *fP, *fA, *fC;          // [Pe][nx][nx] chunk folds / suffix levels (ping)
+  T *gP, *gA, *gC;          // [Pe][nx][nx] suffix levels (pong)
+  T *Pend;                  // [Pe][nx][nx] P at each chunk's right end
+  T *scratch;               // [max(Pe,Pi)][8][slot] per-workgroup scratch
+  size_t slot;              // max(nx, nu)^2
+  int* status;              // [1] 0 ok, 1 not positive definite
+};
+
+// Per-launch control block shared by the iteration kernel and the host.
+struct IterCtl {
+  int32_t it;          // iterations completed (cumulative)
+  int32_t status;      // 0 running, 1 solved, 2 max_iter, 3 numerical, 4 rho change, 5 wait timeout
+  double r_p, r_d;
+  double rho_new;      // proposed rho when status == 4
+};
+
+struct IterParams {
+  int P;               // workgroups (horizon chunks)
+  int nlev;            // ceil(log2 P)
+  double rho, tol;
+  int it0, max_iter;   // iteration counter at launch, global limit
+  int adaptive, sigma;
+  double rho_min, rho_max, rho_tol;
+  double hnorm;        // |(q, r)|_inf
+  uint32_t stamp0;     // stamps of this launch start after stamp0
+};
+
+struct LLBufs {
+  unsigned long long* bwd;   // [nlev+1][P][nx*W]  packed words, W = words per value
+  unsigned long long* fwd;   // [nlev+1][P][nx*W]
+  unsigned long long* red;   // [P][kRed*W]
+  int* abort;                // set when any wait gives up
+};
+constexpr int kRed = 6;      // r_p, r_d, |v|, |z|, |H xi|, |G^T lambda|
+
+template <typename T>
+struct IterArgs {
+  DevProblem<T> pb;
+  DevFactor<T> fc;
+  double *z, *y;             // [m] ADMM state (scaled dual y = lambda / rho), FP64
+  const double *l, *u;       // [m] bounds, FP64
+  double *X, *U;             // [N+1][nx], [N][nu] last primal iterate (FP64)
+  const T* x0;               // [nx]
+  LLBufs ll;
+  IterParams ip;
+  IterCtl* ctl;
+  int Lmax;                  // max stages per chunk
+  int resident;              // chunk operators kept in LDS
+  unsigned long long* prof;  // optional [16] cycle counts per phase (workgroup 0)
+};
+
+template <typename T> int epoch_set_attributes();
+template <typename T>
+int launch_epoch(const DevProblem<T>& pb, const DevEpochWork<T>& ew, const DevFactor<T>& fc,
+                 double rho, int Pe, int Pi, int nlev, hipStream_t st);
+template <typename T> size_t admm_lds_bytes(int nx, int nu, int nc, int nf, int Lmax, int P, bool resident);
+template <typename T> int launch_admm(const IterArgs<T>& args, hipStream_t st);
+
+// Elements of one LDS-resident stage block of the iteration kernel (operators
+// F = [[Abar, B], [K, I]], G = [C | D] and Gamma with odd leading dimensions).
+inline int stage_block_elems_host(int nx, int nu, int nc) {
+  auto odd = [](int x) { return x | 1; };
+  const int nxu = nx + nu;
+  int e = nxu * odd(nxu) + nc * odd(nxu) + nu * odd(nu);
+  return (e + 3) & ~3;
+}
+
+}  // namespace gsls

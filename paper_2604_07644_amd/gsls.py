@@ -1,0 +1,221 @@
+"""ctypes binding of the C ABI in include/gsls.h (argument marshalling only).
+
+Every computation happens in libgsls.so's HIP kernels.  Importing this module
+loads the library and fails loudly if it has not been built; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsls.so")
+
+OK = 0
+ERR_INVALID_ARG, ERR_DIM, ERR_NOT_PD, ERR_NUMERICAL, ERR_OOM, ERR_HIP, ERR_STATE = range(-1, -8, -1)
+SOLVED, MAX_ITER, NUMERICAL_FAIL = 1, 2, 3
+HOST, DEVICE = 0, 1
+MIXED, FP64 = 0, 1
+
+_dp = ct.POINTER(ct.c_double)
+
+
+class QPDesc(ct.Structure):
+    _fields_ = [("N", ct.c_int32), ("nx", ct.c_int32), ("nu", ct.c_int32), ("nc", ct.c_int32),
+                ("nf", ct.c_int32), ("mem", ct.c_int32),
+                ("A", _dp), ("B", _dp), ("b", _dp), ("Q", _dp), ("R", _dp), ("S", _dp),
+                ("q", _dp), ("r", _dp), ("C", _dp), ("D", _dp), ("CN", _dp), ("l", _dp), ("u", _dp)]
+
+
+class Settings(ct.Structure):
+    _fields_ = [("precision", ct.c_int32), ("max_iter", ct.c_int32), ("adaptive_rho", ct.c_int32),
+                ("sigma", ct.c_int32), ("rho_min", ct.c_double), ("rho_max", ct.c_double),
+                ("rho_tol", ct.c_double), ("chunks_epoch", ct.c_int32), ("chunks_iter", ct.c_int32)]
+
+
+class Result(ct.Structure):
+    _fields_ = [("status", ct.c_int32), ("iterations", ct.c_int32), ("rho_updates", ct.c_int32),
+                ("factorizations", ct.c_int32), ("r_p", ct.c_double), ("r_d", ct.c_double),
+                ("rho", ct.c_double), ("ms_total", ct.c_double), ("ms_factor", ct.c_double),
+                ("ms_iterate", ct.c_double)]
+
+    def asdict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class GslsError(RuntimeError):
+    def __init__(self, code, where=""):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libgsls.so not built at {LIB_PATH}; run paper_2604_07644_amd/build.py")
+    lib = ct.CDLL(LIB_PATH)
+    P = ct.c_void_p
+    sig = {
+        "gsls_default_settings": (None, [ct.POINTER(Settings)]),
+        "gsls_strerror": (ct.c_char_p, [ct.c_int]),
+        "gsls_validate_desc": (ct.c_int, [ct.POINTER(QPDesc)]),
+        "gsls_qp_setup": (ct.c_int, [ct.POINTER(QPDesc), ct.POINTER(Settings), P, ct.POINTER(P)]),
+        "gsls_qp_update_bounds": (ct.c_int, [P, _dp, _dp]),
+        "gsls_qp_solve": (ct.c_int, [P, _dp, ct.c_double, ct.c_double, ct.POINTER(Result)]),
+        "gsls_qp_solve_warm": (ct.c_int, [P, _dp, ct.c_double, ct.c_double, _dp, _dp, ct.POINTER(Result)]),
+        "gsls_qp_get": (ct.c_int, [P, _dp, _dp, _dp, _dp]),
+        "gsls_qp_free": (None, [P]),
+        "gsls_sls_solve": (ct.c_int, [P, _dp, _dp, _dp, _dp, _dp, ct.c_int32, ct.c_double, _dp, _dp, _dp, _dp]),
+        "gsls_sls_solve_batch": (ct.c_int, [P, ct.c_int32, _dp, _dp, _dp, _dp, _dp, ct.c_int32, ct.c_double,
+                                            _dp, _dp, _dp]),
+        "gsls_sls_tau": (ct.c_int, [P, _dp, _dp, _dp, ct.c_double, _dp]),
+        "gsls_debug_phase_cycles": (ct.c_int, [P, ct.c_int32, _dp, ct.POINTER(ct.c_int32)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def strerror(code: int) -> str:
+    return lib.gsls_strerror(int(code)).decode()
+
+
+def default_settings(**kw) -> Settings:
+    s = Settings()
+    lib.gsls_default_settings(ct.byref(s))
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _f64(a, shape=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def make_desc(prob):
+    """QPDesc with host pointers for a workloads.QPProblem; returns (desc, keepalive)."""
+    N, nx, nu, nc, nf = prob.N, prob.nx, prob.nu, prob.nc, prob.nf
+    arrs = dict(A=_f64(prob.A), B=_f64(prob.B), b=_f64(prob.b), Q=_f64(prob.Q), R=_f64(prob.R),
+                S=_f64(prob.S), q=_f64(prob.q), r=_f64(prob.r), C=_f64(prob.C), D=_f64(prob.D),
+                CN=_f64(prob.CN, (nf, nx)) if nf else None, l=_f64(prob.l), u=_f64(prob.u))
+    d = QPDesc(N=N, nx=nx, nu=nu, nc=nc, nf=nf, mem=HOST)
+    for k, v in arrs.items():
+        setattr(d, k, _ptr(v))
+    return d, arrs
+
+
+def validate_desc(prob) -> int:
+    d, keep = make_desc(prob)
+    return lib.gsls_validate_desc(ct.byref(d))
+
+
+class QP:
+    """One QP handle (gsls_qp_setup ... gsls_qp_free)."""
+
+    def __init__(self, prob, settings: Optional[Settings] = None, stream=None, **kw):
+        self.prob = prob
+        self.settings = settings or default_settings(**kw)
+        d, keep = make_desc(prob)
+        h = ct.c_void_p()
+        rc = lib.gsls_qp_setup(ct.byref(d), ct.byref(self.settings),
+                               ct.c_void_p(stream) if stream else None, ct.byref(h))
+        if rc != OK:
+            raise GslsError(rc, "gsls_qp_setup")
+        self.h = h
+        self.result = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.gsls_qp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def update_bounds(self, l, u):
+        l = _f64(l); u = _f64(u)
+        rc = lib.gsls_qp_update_bounds(self.h, _ptr(l), _ptr(u))
+        if rc != OK:
+            raise GslsError(rc, "gsls_qp_update_bounds")
+
+    def solve(self, x0=None, rho=1.0, tol=1e-5, z0=None, y0=None) -> dict:
+        x0 = _f64(self.prob.x0 if x0 is None else x0)
+        res = Result()
+        if z0 is None:
+            rc = lib.gsls_qp_solve(self.h, _ptr(x0), rho, tol, ct.byref(res))
+        else:
+            z0 = _f64(z0); y0 = _f64(y0)
+            rc = lib.gsls_qp_solve_warm(self.h, _ptr(x0), rho, tol, _ptr(z0), _ptr(y0), ct.byref(res))
+        if rc != OK:
+            raise GslsError(rc, "gsls_qp_solve")
+        self.result = res.asdict()
+        return self.result
+
+    def get(self) -> dict:
+        p = self.prob
+        X = np.zeros((p.N + 1, p.nx)); U = np.zeros((p.N, p.nu)); z = np.zeros(p.m); lam = np.zeros(p.m)
+        rc = lib.gsls_qp_get(self.h, _ptr(X), _ptr(U), _ptr(z), _ptr(lam))
+        if rc != OK:
+            raise GslsError(rc, "gsls_qp_get")
+        return dict(X=X, U=U, z=z, lam=lam)
+
+    def phase_cycles(self, enable=-1):
+        """Per-phase shader cycles of the iteration kernel (see gsls.h) and the
+        chunk layout (Pe, Pi, resident, Lmax)."""
+        out = np.zeros(16)
+        lay = (ct.c_int32 * 4)()
+        rc = lib.gsls_debug_phase_cycles(self.h, int(enable), _ptr(out), lay)
+        if rc != OK:
+            raise GslsError(rc, "gsls_debug_phase_cycles")
+        return out, tuple(lay)
+
+    def sls_solve(self, E, tau, Qbar, Rbar, QbarN, rownorm=2, wbound=1.0, want_phi=True):
+        p = self.prob
+        N, nx, nu, nc, nf = p.N, p.nx, p.nu, p.nc, p.nf
+        Px = np.zeros((N * (N + 1) // 2, nx, nx)) if want_phi else None
+        Pu = np.zeros((N * (N - 1) // 2, nu, nx)) if want_phi else None
+        h = np.zeros((N, nc)); hf = np.zeros(nf)
+        E = _f64(E); tau = _f64(tau); Qbar = _f64(Qbar); Rbar = _f64(Rbar); QbarN = _f64(QbarN)
+        rc = lib.gsls_sls_solve(self.h, _ptr(E), _ptr(tau), _ptr(Qbar), _ptr(Rbar), _ptr(QbarN),
+                                int(rownorm), float(wbound), _ptr(Px), _ptr(Pu), _ptr(h), _ptr(hf))
+        if rc != OK:
+            raise GslsError(rc, "gsls_sls_solve")
+        return dict(Phi_x=Px, Phi_u=Pu, h=h, hf=hf)
+
+    def sls_solve_batch(self, E, taus, Qbar, Rbar, QbarN, rownorm=2, wbound=1.0):
+        p = self.prob
+        cnt = len(taus)
+        h = np.zeros((cnt, p.N, p.nc)); hf = np.zeros((cnt, p.nf)); ms = np.zeros(1)
+        E = _f64(E); tau = _f64(np.concatenate([np.asarray(t).reshape(-1) for t in taus]))
+        Qbar = _f64(Qbar); Rbar = _f64(Rbar); QbarN = _f64(QbarN)
+        rc = lib.gsls_sls_solve_batch(self.h, cnt, _ptr(E), _ptr(tau), _ptr(Qbar), _ptr(Rbar), _ptr(QbarN),
+                                      int(rownorm), float(wbound), _ptr(h), _ptr(hf), _ptr(ms))
+        if rc != OK:
+            raise GslsError(rc, "gsls_sls_solve_batch")
+        return dict(h=h, hf=hf, ms=float(ms[0]))
+
+    def sls_tau(self, lam, Phi_x, Phi_u, eps=1e-8):
+        p = self.prob
+        tau = np.zeros(p.N * p.N * p.nc + p.N * p.nf)
+        lam = _f64(lam); Phi_x = _f64(Phi_x); Phi_u = _f64(Phi_u)
+        rc = lib.gsls_sls_tau(self.h, _ptr(lam), _ptr(Phi_x), _ptr(Phi_u), float(eps), _ptr(tau))
+        if rc != OK:
+            raise GslsError(rc, "gsls_sls_tau")
+        return tau

@@ -127,6 +127,7 @@ struct SolverBase {
                         const double* Rb, const double* QbN, int rownorm, double wbound, double* h,
                         double* hf, double* ms) = 0;
   virtual int phase_cycles(int enable, double* out, int* chunks) = 0;
+  virtual int sls_tau(const double* lam, const double* Phx, const double* Phu, double eps, double* tau) = 0;
 };
 
 template <typename T>
@@ -433,13 +434,176 @@ struct Solver : SolverBase {
     return GSLS_OK;
   }
 
-  int sls(const double*, const double*, const double*, const double*, const double*, int, double, double*,
-          double*, double*, double*) override {
-    return GSLS_ERR_STATE;
+  // ------------------------------------------------------------ SLS
+  struct SlsBuf {
+    bool ready = false;
+    int grid = 0, cap = 0;                  // work-queue grid, instance capacity
+    float *A = nullptr, *B = nullptr, *G = nullptr, *CN = nullptr;
+    float *E = nullptr, *Qb = nullptr, *Rb = nullptr, *QbN = nullptr;
+    float *tau = nullptr, *Kst = nullptr, *hj = nullptr, *hfj = nullptr, *Phx = nullptr, *Phu = nullptr;
+    double *h = nullptr, *hf = nullptr, *lam = nullptr, *taud = nullptr;
+    unsigned* counter = nullptr;
+    int* status = nullptr;
+  } sb;
+  DevArena sls_arena;
+
+  int sls_prepare(int count) {
+    const int N = hd.N, nx = hd.nx, nu = hd.nu, nc = hd.nc, nf = hd.nf, nxu = nx + nu;
+    auto cvt = [&](const std::vector<double>& v) {
+      std::vector<float> t(v.size());
+      for (size_t i = 0; i < v.size(); ++i) t[i] = (float)v[i];
+      return t;
+    };
+    auto upf = [&](const std::vector<float>& v) {
+      float* p = sls_arena.alloc<float>(v.size());
+      if (p && hipMemcpyAsync(p, v.data(), v.size() * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
+        sls_arena.ok = false;
+      return p;
+    };
+    if (!sb.ready) {
+      sb.A = upf(cvt(hd.A));
+      sb.B = upf(cvt(hd.B));
+      std::vector<float> G((size_t)N * nc * nxu);
+      for (int k = 0; k < N; ++k)
+        for (int r = 0; r < nc; ++r) {
+          for (int j = 0; j < nx; ++j) G[((size_t)k * nc + r) * nxu + j] = (float)hd.C[((size_t)k * nc + r) * nx + j];
+          for (int j = 0; j < nu; ++j) G[((size_t)k * nc + r) * nxu + nx + j] = (float)hd.D[((size_t)k * nc + r) * nu + j];
+        }
+      sb.G = upf(G);
+      sb.CN = upf(cvt(hd.CN));
+      sb.E = sls_arena.alloc<float>((size_t)N * nx * nx);
+      sb.Qb = sls_arena.alloc<float>((size_t)nx * nx);
+      sb.Rb = sls_arena.alloc<float>((size_t)nu * nu);
+      sb.QbN = sls_arena.alloc<float>((size_t)nx * nx);
+      sb.grid = sls_grid(nx, nu, nc, nf);
+      if (sb.grid <= 0) return GSLS_ERR_HIP;
+      sb.Kst = sls_arena.alloc<float>((size_t)sb.grid * N * nu * nx);
+      sb.Phx = sls_arena.alloc<float>((size_t)N * (N + 1) / 2 * nx * nx);
+      sb.Phu = sls_arena.alloc<float>((size_t)std::max(1, N * (N - 1) / 2) * nu * nx);
+      sb.lam = sls_arena.alloc<double>((size_t)hd.m);
+      sb.taud = sls_arena.alloc<double>((size_t)N * N * nc + (size_t)N * nf);
+      sb.counter = sls_arena.alloc<unsigned>(1);
+      sb.status = sls_arena.alloc<int>(1);
+      if (!sls_arena.ok) return GSLS_ERR_OOM;
+      sb.ready = true;
+    }
+    if (count > sb.cap) {
+      const size_t ts = (size_t)N * N * nc + (size_t)N * nf;
+      sb.tau = sls_arena.alloc<float>((size_t)count * ts);
+      sb.hj = sls_arena.alloc<float>((size_t)count * N * N * nc);
+      sb.hfj = sls_arena.alloc<float>((size_t)count * N * std::max(nf, 1));
+      sb.h = sls_arena.alloc<double>((size_t)count * N * std::max(nc, 1));
+      sb.hf = sls_arena.alloc<double>((size_t)count * std::max(nf, 1));
+      if (!sls_arena.ok) return GSLS_ERR_OOM;
+      sb.cap = count;
+    }
+    return GSLS_OK;
   }
-  int sls_batch(int, const double*, const double*, const double*, const double*, const double*, int, double,
-                double*, double*, double*) override {
-    return GSLS_ERR_STATE;
+
+  int sls_common(int count, const double* E, const double* tau, const double* Qb, const double* Rb,
+                 const double* QbN, int rownorm, double wbound, bool want_phi, float* ms) {
+    const int N = hd.N, nx = hd.nx, nu = hd.nu, nc = hd.nc, nf = hd.nf;
+    if (!E || !Qb || !Rb || !QbN || count < 1) return GSLS_ERR_INVALID_ARG;
+    if (rownorm != 1 && rownorm != 2) return GSLS_ERR_INVALID_ARG;
+    if (!std::isfinite(wbound) || wbound < 0) return GSLS_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = sls_prepare(count))) return rc;
+    const size_t ts = (size_t)N * N * nc + (size_t)N * nf;
+    auto h2d = [&](float* dst, const double* src, size_t n) -> int {
+      std::vector<float> t(n);
+      for (size_t i = 0; i < n; ++i) {
+        if (!std::isfinite(src[i])) return GSLS_ERR_INVALID_ARG;
+        t[i] = (float)src[i];
+      }
+      if (hipMemcpyAsync(dst, t.data(), n * 4, hipMemcpyHostToDevice, stream) != hipSuccess) return GSLS_ERR_HIP;
+      return hipStreamSynchronize(stream) == hipSuccess ? GSLS_OK : GSLS_ERR_HIP;
+    };
+    if ((rc = h2d(sb.E, E, (size_t)N * nx * nx))) return rc;
+    if ((rc = h2d(sb.Qb, Qb, (size_t)nx * nx))) return rc;
+    if ((rc = h2d(sb.Rb, Rb, (size_t)nu * nu))) return rc;
+    if ((rc = h2d(sb.QbN, QbN, (size_t)nx * nx))) return rc;
+    if (tau) {
+      if ((rc = h2d(sb.tau, tau, (size_t)count * ts))) return rc;
+    } else if (hipMemsetAsync(sb.tau, 0, (size_t)count * ts * 4, stream) != hipSuccess) {
+      return GSLS_ERR_HIP;
+    }
+    if (hipMemsetAsync(sb.counter, 0, 4, stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (hipMemsetAsync(sb.status, 0, 4, stream) != hipSuccess) return GSLS_ERR_HIP;
+    SlsArgs sa{};
+    sa.N = N; sa.nx = nx; sa.nu = nu; sa.nc = nc; sa.nf = nf; sa.count = count;
+    sa.A = sb.A; sa.B = sb.B; sa.G = sb.G; sa.CN = sb.CN; sa.E = sb.E; sa.tau = sb.tau;
+    sa.Qb = sb.Qb; sa.Rb = sb.Rb; sa.QbN = sb.QbN; sa.rownorm = rownorm; sa.squared = 0;
+    sa.Kst = sb.Kst; sa.hj = sb.hj; sa.hfj = sb.hfj;
+    sa.Phx = want_phi ? sb.Phx : nullptr; sa.Phu = want_phi ? sb.Phu : nullptr;
+    sa.counter = sb.counter; sa.status = sb.status;
+    if (hipEventRecord(ev[0], stream) != hipSuccess) return GSLS_ERR_HIP;
+    if ((rc = launch_sls(sa, sb.grid, stream))) return rc;
+    if ((rc = launch_sls_sum(N, nc, nf, count, (float)wbound, sb.hj, sb.hfj, sb.h, sb.hf, stream))) return rc;
+    if (hipEventRecord(ev[1], stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (hipMemcpyAsync(status_h, sb.status, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess)
+      return GSLS_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (*status_h) return GSLS_ERR_NOT_PD;
+    if (ms) (void)hipEventElapsedTime(ms, ev[0], ev[1]);
+    return GSLS_OK;
+  }
+
+  int d2h(double* dst, const double* src, size_t n) {
+    if (!dst || n == 0) return GSLS_OK;
+    return hipMemcpy(dst, src, n * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess ? GSLS_OK : GSLS_ERR_HIP;
+  }
+  int d2h_f(double* dst, const float* src, size_t n) {
+    if (!dst || n == 0) return GSLS_OK;
+    std::vector<float> t(n);
+    if (hipMemcpy(t.data(), src, n * 4, hipMemcpyDeviceToHost) != hipSuccess) return GSLS_ERR_HIP;
+    for (size_t i = 0; i < n; ++i) dst[i] = t[i];
+    return GSLS_OK;
+  }
+
+  int sls(const double* E, const double* tau, const double* Qb, const double* Rb, const double* QbN,
+          int rownorm, double wbound, double* Phx, double* Phu, double* h, double* hf) override {
+    const int N = hd.N, nx = hd.nx, nu = hd.nu, nc = hd.nc, nf = hd.nf;
+    int rc = sls_common(1, E, tau, Qb, Rb, QbN, rownorm, wbound, Phx || Phu, nullptr);
+    if (rc) return rc;
+    if ((rc = d2h_f(Phx, sb.Phx, (size_t)N * (N + 1) / 2 * nx * nx))) return rc;
+    if ((rc = d2h_f(Phu, sb.Phu, (size_t)N * (N - 1) / 2 * nu * nx))) return rc;
+    if ((rc = d2h(h, sb.h, (size_t)N * nc))) return rc;
+    if ((rc = d2h(hf, sb.hf, (size_t)nf))) return rc;
+    return GSLS_OK;
+  }
+
+  int sls_batch(int count, const double* E, const double* tau, const double* Qb, const double* Rb,
+                const double* QbN, int rownorm, double wbound, double* h, double* hf, double* ms) override {
+    const int N = hd.N, nc = hd.nc, nf = hd.nf;
+    float t = 0.f;
+    int rc = sls_common(count, E, tau, Qb, Rb, QbN, rownorm, wbound, false, &t);
+    if (rc) return rc;
+    if (ms) *ms = t;
+    if ((rc = d2h(h, sb.h, (size_t)count * N * nc))) return rc;
+    if ((rc = d2h(hf, sb.hf, (size_t)count * nf))) return rc;
+    return GSLS_OK;
+  }
+
+  int sls_tau(const double* lam, const double* Phx, const double* Phu, double eps, double* tau) override {
+    const int N = hd.N, nx = hd.nx, nu = hd.nu, nc = hd.nc, nf = hd.nf;
+    if (!lam || !Phx || !tau || (N > 1 && !Phu) || !(eps > 0.0)) return GSLS_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = sls_prepare(1))) return rc;
+    auto h2d = [&](float* dst, const double* src, size_t n) -> int {
+      std::vector<float> t(n);
+      for (size_t i = 0; i < n; ++i) t[i] = (float)src[i];
+      return hipMemcpy(dst, t.data(), n * 4, hipMemcpyHostToDevice) == hipSuccess ? GSLS_OK : GSLS_ERR_HIP;
+    };
+    if ((rc = h2d(sb.Phx, Phx, (size_t)N * (N + 1) / 2 * nx * nx))) return rc;
+    if (N > 1 && (rc = h2d(sb.Phu, Phu, (size_t)N * (N - 1) / 2 * nu * nx))) return rc;
+    if (hipMemcpy(sb.lam, lam, (size_t)hd.m * 8, hipMemcpyHostToDevice) != hipSuccess) return GSLS_ERR_HIP;
+    SlsArgs sa{};
+    sa.N = N; sa.nx = nx; sa.nu = nu; sa.nc = nc; sa.nf = nf; sa.count = 1;
+    sa.G = sb.G; sa.CN = sb.CN; sa.Phx = sb.Phx; sa.Phu = sb.Phu; sa.hj = sb.hj; sa.hfj = sb.hfj;
+    if ((rc = launch_sls_beta(sa, stream))) return rc;
+    if ((rc = launch_sls_tau(N, nc, nf, sb.hj, sb.hfj, sb.lam, eps, sb.taud, stream))) return rc;
+    if (hipStreamSynchronize(stream) != hipSuccess) return GSLS_ERR_HIP;
+    return d2h(tau, sb.taud, (size_t)N * N * nc + (size_t)N * nf);
   }
 };
 
@@ -579,8 +743,8 @@ int gsls_sls_solve_batch(gsls_qp* h, int32_t count, const double* E, const doubl
 
 int gsls_sls_tau(gsls_qp* h, const double* lambda, const double* Phi_x, const double* Phi_u, double eps,
                  double* tau) {
-  (void)h; (void)lambda; (void)Phi_x; (void)Phi_u; (void)eps; (void)tau;
-  return GSLS_ERR_STATE;
+  if (!h) return GSLS_ERR_INVALID_ARG;
+  return h->impl->sls_tau(lambda, Phi_x, Phi_u, eps, tau);
 }
 
 }  // extern "C"

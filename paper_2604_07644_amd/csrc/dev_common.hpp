@@ -148,6 +148,67 @@ __device__ void wg_symmetrize(int n, T* P, int ld) {
   __syncthreads();
 }
 
+
+// ------------------------------------------------------- MFMA GEMM (FP32)
+// C = alpha * op(A) * op(B) + beta * C on the matrix cores, op(A) m x k and
+// op(B) k x n with A and B in LDS (op = transpose when ta / tb), C anywhere.
+// The output is cut into 16 x 16 tiles handed round-robin to the four waves;
+// a wave accumulates its tile with v_mfma_f32_16x16x4f32, lane l supplying
+// A[i0 + l%16][k0 + l/16] and B[k0 + l/16][j0 + l%16], and holding
+// C[i0 + 4(l/16) + r][j0 + l%16] in accumulator r.  Out-of-range operands are
+// clamped into range and zeroed.  Ends with a barrier.  C must not alias A/B.
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+template <typename PC>
+__device__ inline void wg_mm_f32(int m, int n, int k, float alpha, const LDS float* A, int lda, bool ta,
+                                 const LDS float* B, int ldb, bool tb, float beta, PC C, int ldc) {
+  const int l = lane(), w = wave();
+  const int tn = (n + 15) >> 4, tm = (m + 15) >> 4;
+  const int r16 = l & 15, q = l >> 4;
+  for (int t = w; t < tm * tn; t += 4) {
+    const int ti = t / tn, tj = t - ti * tn;
+    const int i = ti * 16 + r16, j = tj * 16 + r16;
+    const int ic = min(i, m - 1), jc = min(j, n - 1);
+    const float ma = i < m ? 1.f : 0.f, mb = j < n ? 1.f : 0.f;
+    mfma_f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int k0 = 0; k0 < k; k0 += 4) {
+      const int kk = k0 + q;
+      const int kc = min(kk, k - 1);
+      const float mk = kk < k ? 1.f : 0.f;
+      const float av = ta ? A[kc * lda + ic] : A[ic * lda + kc];
+      const float bv = tb ? B[jc * ldb + kc] : B[kc * ldb + jc];
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av * ma * mk, bv * mb, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ii = ti * 16 + 4 * q + r, jj = tj * 16 + r16;
+      if (ii < m && jj < n) {
+        float v = alpha * acc[r];
+        if (beta != 0.f) v += beta * C[ii * ldc + jj];
+        C[ii * ldc + jj] = v;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Sum (2-norm or 1-norm) of each row of the m x n matrix M (LDS): out[r] for
+// r < m, one wave per row at a time.
+__device__ inline void wg_row_norms(int m, int n, const LDS float* M, int ld, int rownorm, float* out,
+                                    bool squared) {
+  const int l = lane(), w = wave();
+  for (int r = w; r < m; r += 4) {
+    float s = 0.f;
+    for (int c = l; c < n; c += 64) {
+      const float v = M[r * ld + c];
+      s += rownorm == 1 ? fabsf(v) : v * v;
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (l == 0) out[r] = (rownorm == 1 || squared) ? s : sqrtf(s);
+  }
+}
+
 // -------------------------------------------------- FP64 Gauss-Jordan inverse
 constexpr int kGJRows = kMaxNx / 4;   // rows per wave
 // Inverse of the n x n matrix held in the left half of Aug = [M | I] (LDS,

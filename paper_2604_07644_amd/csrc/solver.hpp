@@ -99,4 +99,27 @@ inline int stage_block_elems_host(int nx, int nu, int nc) {
   return (e + 3) & ~3;
 }
 
+struct SlsArgs {
+  int N, nx, nu, nc, nf, count;
+  const float *A, *B, *G, *CN;     // problem (FP32): [N][nx][nx], [N][nx][nu], [N][nc][nx+nu], [nf][nx]
+  const float *E;                  // [N][nx][nx]
+  const float *tau;                // [count][N*N*nc + N*nf]
+  const float *Qb, *Rb, *QbN;      // [nx][nx], [nu][nu], [nx][nx]
+  int rownorm;                     // 2 or 1
+  int squared;                     // store squared row norms (beta of App. B) instead
+  float* Kst;                      // [grid][N][nu][nx] per-workgroup gain store
+  float* hj;                       // [count][N][N][nc]: row norms for (k, j), k > j
+  float* hfj;                      // [count][N][nf]
+  float *Phx, *Phu;                // optional Phi^x / Phi^u of instance 0 (packed as in gsls.h)
+  unsigned* counter;               // work queue head
+  int* status;                     // 1 if a Z_uu block was not positive definite
+};
+int sls_grid(int nx, int nu, int nc, int nf);
+int launch_sls(const SlsArgs& args, int grid, hipStream_t st);
+int launch_sls_sum(int N, int nc, int nf, int count, float wbound, const float* hj, const float* hfj, double* h,
+                   double* hf, hipStream_t st);
+int launch_sls_beta(const SlsArgs& args, hipStream_t st);
+int launch_sls_tau(int N, int nc, int nf, const float* betaj, const float* betafj, const double* lam, double eps,
+                   double* tau, hipStream_t st);
+
 }  // namespace gsls

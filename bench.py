@@ -60,6 +60,79 @@ def make_workload(name):
     return p, desc
 
 
+def sls_flops(p):
+    """Algorithmic FP32 flops of one SLS instance: per (column j, stage k > j)
+    the Riccati step Z = [A|B]^T P [A|B] + G^T diag(tau) G, K = -Z_uu^{-1} Z_ux,
+    P = Z_xx + Z_ux^T K, and the forward step Phi^u = K Phi^x, margins
+    G [Phi^x; Phi^u], Phi^x' = [A|B] [Phi^x; Phi^u]; plus the terminal terms."""
+    N, nx, nu, nc, nf = p.N, p.nx, p.nu, p.nc, p.nf
+    nxu = nx + nu
+    bwd = 2 * nx * nx * nxu + 2 * nxu * nxu * nx + 2 * nxu * nxu * nc + 2 * nu * nu * nx + 2 * nx * nx * nu
+    fwd = 2 * nu * nx * nx + 2 * nc * nxu * nx + 2 * nx * nxu * nx
+    steps = N * (N - 1) // 2
+    return steps * (bwd + fwd) + N * (2 * nx * nx * nf + 2 * nf * nx * nx)
+
+
+def bench_sls(args):
+    """SLS batch: 64 quadruped-shaped instances (nx=61, nu=12, N=64, 40 rows),
+    tau from each instance's nominal ADMM multipliers (App. B), |w|_inf <= 0.01."""
+    import torch
+    from paper_2604_07644_amd import gsls, workloads as W
+    count = 64
+    probs, E, wb = W.sls_batch(count)
+    p0 = probs[0]
+    Qb, Rb, QbN = np.eye(p0.nx), np.eye(p0.nu), np.eye(p0.nx)
+    q = gsls.QP(p0, gsls.default_settings(precision=gsls.MIXED),
+                stream=torch.cuda.current_stream().cuda_stream)
+    base = q.sls_solve(E, None, Qb, Rb, QbN, rownorm=1, wbound=wb)       # tau = 0
+    taus = []
+    for p in probs:
+        q.update_bounds(p.l, p.u)
+        q.solve(x0=p.x0, rho=1.0, tol=TOL)
+        lam = q.get()["lam"]
+        taus.append(q.sls_tau(lam, base["Phi_x"], base["Phi_u"]))
+    for _ in range(args.warmup):
+        q.sls_solve_batch(E, taus, Qb, Rb, QbN, rownorm=1, wbound=wb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dev_ms = []
+    for _ in range(args.steps):
+        dev_ms.append(q.sls_solve_batch(E, taus, Qb, Rb, QbN, rownorm=1, wbound=wb)["ms"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    q.close()
+    flops = sls_flops(p0) * count
+    ms = float(np.mean(dev_ms))
+    achieved = flops / (ms * 1e-3) / 1e12
+    line = {
+        "metric": "SLS instances/s (Phi^x, Phi^u and reachable-set margins)",
+        "value": count * args.steps / wall, "unit": "instances/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic (seeded generator)",
+        "config": {"workload": "SLS batch of 64 quadruped-shaped instances, nx=61 nu=12 N=64, 40 rows/stage, "
+                               "|w|_inf <= 0.01, tau from nominal ADMM multipliers",
+                   "device_ms_per_batch": ms},
+        "roofline": {"kernel": "k_sls (persistent SLS columns)", "bound": "mfma", "achieved": achieved,
+                     "peak": 157.3, "unit": "TFLOP/s", "frac": achieved / 157.3, "traffic": None,
+                     "flops_per_batch": flops},
+    }
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            oracle.sls_solve(probs[n % count], E, taus[n % count], Qb, Rb, QbN, rownorm=1, wbound=wb,
+                             want_phi=False)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_budget or n >= 50:
+                break
+        line["cpu_baseline"] = {"value": n / el, "unit": "instances/s", "cores": 1, "kind": "oracle",
+                                "sample": f"{n} instances of the same batch (FP64 per-column Riccati)"}
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(p, budget_s=10.0):
     import oracle
     t0 = time.perf_counter()
@@ -91,6 +164,10 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+
+    if args.workload == "sls":
+        bench_sls(args)
+        return
 
     import torch
     from paper_2604_07644_amd import gsls

@@ -201,6 +201,31 @@ int gsls_sls_solve_batch(gsls_qp* h, int32_t count, const double* E, const doubl
 int gsls_sls_tau(gsls_qp* h, const double* lambda, const double* Phi_x, const double* Phi_u,
                  double eps, double* tau);
 
+/* ------------------------------------------------------------ batches ---
+ * Many independent QPs of uneven shape solved in one persistent launch
+ * (captured in a HIP graph and replayed on later calls): each workgroup of
+ * the launch takes whole instances from a device work queue, largest first,
+ * and runs the ADMM of gsls_qp_solve for each (mixed precision).  Instances
+ * whose rows are exactly the box [x_k; u_k] (C = [I; 0], D = [0; I]) and whose
+ * terminal rows are x_N or absent skip the constraint-map products.
+ * Limits: nx + nu <= 96, nc <= 64 (box: nc = nx + nu), host memory. */
+typedef struct gsls_batch gsls_batch;
+
+int gsls_qp_setup_batch(const gsls_qp_desc* descs, int32_t count, const gsls_settings* settings,
+                        void* stream, gsls_batch** out);
+
+/* x0[c] initial state, rho[c] initial penalty of instance c; z0, y0 NULL for a
+ * cold start of every instance, else per instance NULL (cold) or the starting
+ * iterate (length N*nc+nf, y the scaled dual).  out[count] receives each
+ * instance's result; *ms (nullable) the device time of the launch. */
+int gsls_qp_solve_batch(gsls_batch* b, const double* const* x0, const double* rho, double tol,
+                        const double* const* z0, const double* const* y0, gsls_result* out, double* ms);
+
+/* Solution of instance index after gsls_qp_solve_batch (host buffers, any NULL). */
+int gsls_batch_get(gsls_batch* b, int32_t index, double* X, double* U, double* z, double* lambda);
+
+void gsls_batch_free(gsls_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -53,10 +53,10 @@ static bool finite_all(const double* p, size_t n) {
   return true;
 }
 
-static int check_dims(const gsls_qp_desc* d) {
+static int check_dims(const gsls_qp_desc* d, int max_rows = GSLS_MAX_NC) {
   if (!d) return GSLS_ERR_INVALID_ARG;
   if (d->N < 1 || d->N > GSLS_MAX_N || d->nx < 1 || d->nx > GSLS_MAX_NX || d->nu < 1 ||
-      d->nu > GSLS_MAX_NU || d->nc < 0 || d->nc > GSLS_MAX_NC || d->nf < 0 || d->nf > GSLS_MAX_NC)
+      d->nu > GSLS_MAX_NU || d->nc < 0 || d->nc > max_rows || d->nf < 0 || d->nf > max_rows)
     return GSLS_ERR_DIM;
   if (d->mem != GSLS_HOST && d->mem != GSLS_DEVICE) return GSLS_ERR_INVALID_ARG;
   if (!d->A || !d->B || !d->Q || !d->R || !d->l || !d->u) return GSLS_ERR_INVALID_ARG;
@@ -644,13 +644,28 @@ const char* gsls_strerror(int code) {
   }
 }
 
-static int check_settings(const gsls_settings* s) {
+}  // extern "C"
+
+namespace gsls {
+int check_settings(const gsls_settings* s) {
   if (s->precision != GSLS_MIXED && s->precision != GSLS_FP64) return GSLS_ERR_INVALID_ARG;
   if (s->max_iter < 1 || s->sigma < 1 || !(s->rho_min > 0) || !(s->rho_max >= s->rho_min) ||
       !(s->rho_tol > 1.0) || s->chunks_epoch < 0 || s->chunks_iter < 0 || s->chunks_iter > 256)
     return GSLS_ERR_INVALID_ARG;
   return GSLS_OK;
 }
+
+int validate_host_desc(const gsls_qp_desc* desc, int max_rows) {
+  int rc = check_dims(desc, max_rows);
+  if (rc) return rc;
+  if (desc->mem != GSLS_HOST) return GSLS_ERR_INVALID_ARG;
+  HostDesc h;
+  if ((rc = stage_to_host(desc, &h))) return rc;
+  return validate_host(h);
+}
+}  // namespace gsls
+
+extern "C" {
 
 int gsls_validate_desc(const gsls_qp_desc* desc) {
   int rc = gsls::check_dims(desc);
@@ -669,7 +684,7 @@ int gsls_qp_setup(const gsls_qp_desc* desc, const gsls_settings* settings, void*
   gsls_settings s;
   gsls_default_settings(&s);
   if (settings) s = *settings;
-  if ((rc = check_settings(&s))) return rc;
+  if ((rc = gsls::check_settings(&s))) return rc;
   gsls::HostDesc h;
   if ((rc = gsls::stage_to_host(desc, &h))) return rc;
   if ((rc = gsls::validate_host(h))) return rc;

@@ -1,0 +1,789 @@
+// Batched ADMM QP solver: many independent LTV-QPs of uneven shape in one
+// persistent launch (Sec. III-C / IV-A of the paper applied per instance).
+//
+// A workgroup pulls whole instances from a device work queue (largest first)
+// and runs for each: the factor epoch (backward Riccati recursion with the
+// augmented costs of eq. (augmented_matrices); products on the FP32 matrix
+// cores, the nu x nu inverse in FP64), then ADMM iterations whose x-update
+// evaluates the cached affine map of eq. (gains_cache) (backward pass for p,
+// forward roll-out, as in the single-instance kernel but sequential over the
+// horizon inside the workgroup), the projection / dual update and the
+// residuals, with the OSQP-style rho adaptation re-running the epoch when rho
+// changes.  State, projection and residuals are FP64; after the first
+// iteration of each epoch the affine map is applied to the increment of
+// w = y - z with FP64 accumulation (see iterate.hip).
+//
+// Box fast path: when every stage's rows are exactly [x; u] (C = [I; 0],
+// D = [0; I]) and the terminal rows are x_N or absent, G = I and the
+// products with G and G^T are skipped.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "dev_common.hpp"
+#include "solver.hpp"
+
+namespace gsls {
+
+struct BInst {
+  int N, nx, nu, nc, nf, box, m;
+  long long oA, oB, ob, oQ, oR, oS, oq, orr, oG, oCN, ox0;  // float pool: problem
+  long long oF, oGam, oev, ofv, okff;                      // float pool: epoch outputs, gains
+  long long ol, ou, oz, oy, ov, owp, oX, oU;                // double pool
+};
+
+struct BResult {
+  int status, iterations, rho_updates, factorizations;
+  double r_p, r_d, rho;
+};
+
+struct BatchArgs {
+  const BInst* inst;
+  const int* order;            // instance order (largest first)
+  int count;
+  float* fp;                   // float pool
+  double* dp;                  // double pool
+  const double* rho0;          // [count]
+  double tol;
+  int max_iter, adaptive, sigma;
+  double rho_min, rho_max, rho_tol;
+  BResult* res;                // [count]
+  unsigned* counter;
+  int* warm;                   // [count] 1: start from the given z, y
+};
+
+constexpr int kBV = 128;       // work-vector length (>= nx + nu, >= nc)
+constexpr int kBatchMaxNxu = 96;
+
+__host__ __device__ inline int bodd(int x) { return x | 1; }
+
+struct BLayout {
+  int ldP, ldW, ldZ, ldAB, ldG, ldY;
+  size_t P, W, Z, AB, G, Y, vec, bytes;
+  size_t aug, dg, red, perm;   // FP64 / int scratch inside the W region (byte offsets)
+};
+// nc: rows held in the G buffer (0 on the box fast path, else max(nc, nf)).
+// Float regions start on 16-byte boundaries.  The Gauss-Jordan block
+// ([Z_uu | I] in FP64, pivots) and the reduction buffer of the iterations
+// live in the W region, which is dead while they are in use.
+__host__ __device__ inline BLayout batch_layout(int nx, int nu, int nc) {
+  BLayout L;
+  const int nxu = nx + nu;
+  L.ldP = bodd(nx); L.ldW = bodd(nxu); L.ldZ = bodd(nxu); L.ldAB = bodd(nxu); L.ldG = bodd(nxu);
+  L.ldY = bodd(nx);
+  auto r4 = [](size_t v) { return (v + 3) & ~(size_t)3; };
+  const size_t aug_d = (size_t)2 * nu * nu, dg_d = 32, red_d = kWG, perm_d = 32;
+  const size_t wfl = r4((size_t)(nx > nc ? nx : nc) * L.ldW);
+  const size_t afl = 2 * (aug_d + dg_d + red_d + perm_d);
+  size_t o = 0;
+  L.P = o; o += r4((size_t)nx * L.ldP);
+  L.W = o; o += wfl > afl ? wfl : afl;
+  L.Z = o; o += r4((size_t)nxu * L.ldZ);
+  L.AB = o; o += r4((size_t)nx * L.ldAB);
+  L.G = o; o += r4((size_t)nc * L.ldG);
+  L.Y = o; o += r4((size_t)nu * L.ldY);
+  L.vec = o; o += 8 * kBV + 512;
+  L.bytes = o * 4;
+  L.aug = L.W * 4;
+  L.dg = L.aug + aug_d * 8;
+  L.red = L.dg + dg_d * 8;
+  L.perm = L.red + red_d * 8;
+  return L;
+}
+
+// Dynamic LDS available to one workgroup of the batched kernel.
+constexpr size_t kBatchLdsMax = 160 * 1024 - 512;
+
+__device__ inline double wg_max_d(double v, LDS double* s) {
+  s[tid()] = v;
+  __syncthreads();
+  for (int st = kWG / 2; st > 0; st >>= 1) {
+    if (tid() < st) {
+      double a = s[tid()], b = s[tid() + st];
+      s[tid()] = (b > a || b != b) ? b : a;
+    }
+    __syncthreads();
+  }
+  double r = s[0];
+  __syncthreads();
+  return r;
+}
+
+// Factor epoch of one instance for penalty rho.  Returns false if a Z_uu block
+// is not positive definite.
+__device__ bool batch_epoch(const BInst& I, const BatchArgs& a, double rho, LDS char* base) {
+  const int N = I.N, nx = I.nx, nu = I.nu, nc = I.nc, nf = I.nf, nxu = nx + nu;
+  const BLayout lay = batch_layout(nx, nu, I.box ? 0 : (nc > nf ? nc : nf));
+  LDS float* F0 = (LDS float*)base;
+  LDS float* P = F0 + lay.P;
+  LDS float* W = F0 + lay.W;
+  LDS float* Z = F0 + lay.Z;
+  LDS float* AB = F0 + lay.AB;
+  LDS float* G = F0 + lay.G;
+  LDS float* Y = F0 + lay.Y;
+  LDS float* vec = F0 + lay.vec;
+  LDS double* aug = (LDS double*)(base + lay.aug);
+  LDS double* dg = (LDS double*)(base + lay.dg);
+  LDS int* perm = (LDS int*)(base + lay.perm);
+  LDS int* used = perm + 32;
+  float* fp = a.fp;
+  const float fr = (float)rho;
+  // P_N = Q_N + rho C_N^T C_N
+  const float* QN = fp + I.oQ + (size_t)N * nx * nx;
+  for (int r = wave(); r < nx; r += 4)
+    for (int c = lane(); c < nx; c += 64) P[r * lay.ldP + c] = QN[(size_t)r * nx + c];
+  __syncthreads();
+  if (nf > 0) {
+    if (I.box) {
+      for (int r = tid(); r < nx; r += kWG) P[r * lay.ldP + r] += fr;
+    } else {
+      const float* CN = fp + I.oCN;
+      for (int r = wave(); r < nf; r += 4)
+        for (int c = lane(); c < nx; c += 64) G[r * lay.ldG + c] = CN[(size_t)r * nx + c];
+      __syncthreads();
+      wg_mm_f32(nx, nx, nf, fr, G, lay.ldG, true, G, lay.ldG, false, 1.f, P, lay.ldP);
+    }
+  }
+  __syncthreads();
+  for (int k = N - 1; k >= 0; --k) {
+    const float* Ak = fp + I.oA + (size_t)k * nx * nx;
+    const float* Bk = fp + I.oB + (size_t)k * nx * nu;
+    for (int r = wave(); r < nx; r += 4)
+      for (int c = lane(); c < nxu; c += 64)
+        AB[r * lay.ldAB + c] = c < nx ? Ak[(size_t)r * nx + c] : Bk[(size_t)r * nu + (c - nx)];
+    if (!I.box) {
+      const float* Gk = fp + I.oG + (size_t)k * nc * nxu;
+      for (int r = wave(); r < nc; r += 4)
+        for (int c = lane(); c < nxu; c += 64) G[r * lay.ldG + c] = Gk[(size_t)r * nxu + c];
+    }
+    // Pb = P b_k (vec[0..nx))
+    const float* bk = fp + I.ob + (size_t)k * nx;
+    for (int r = wave(); r < nx; r += 4) {
+      float s = 0.f;
+      for (int c = lane(); c < nx; c += 64) s += P[r * lay.ldP + c] * bk[c];
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      if (lane() == 0) vec[r] = s;
+    }
+    __syncthreads();
+    // W = P [A | B];  Z = [A | B]^T W + [[Q, S^T], [S, R]] + rho G^T G
+    wg_mm_f32(nx, nxu, nx, 1.f, P, lay.ldP, false, AB, lay.ldAB, false, 0.f, W, lay.ldW);
+    const float* Qk = fp + I.oQ + (size_t)k * nx * nx;
+    const float* Rk = fp + I.oR + (size_t)k * nu * nu;
+    const float* Sk = fp + I.oS + (size_t)k * nu * nx;
+    for (int r = wave(); r < nxu; r += 4)
+      for (int c = lane(); c < nxu; c += 64) {
+        float v;
+        if (r < nx && c < nx) v = Qk[(size_t)r * nx + c];
+        else if (r >= nx && c >= nx) v = Rk[(size_t)(r - nx) * nu + (c - nx)];
+        else if (r >= nx) v = Sk[(size_t)(r - nx) * nx + c];
+        else v = Sk[(size_t)(c - nx) * nx + r];
+        if (I.box && r == c) v += fr;
+        Z[r * lay.ldZ + c] = v;
+      }
+    __syncthreads();
+    wg_mm_f32(nxu, nxu, nx, 1.f, AB, lay.ldAB, true, W, lay.ldW, false, 1.f, Z, lay.ldZ);
+    if (!I.box && nc > 0) wg_mm_f32(nxu, nxu, nc, fr, G, lay.ldG, true, G, lay.ldG, false, 1.f, Z, lay.ldZ);
+    // Gamma = Z_uu^{-1} (FP64), K = -Gamma Z_ux
+    for (int r = wave(); r < nu; r += 4)
+      for (int c = lane(); c < 2 * nu; c += 64) {
+        const int zr = nx + r, zc = nx + (c < nu ? c : 0);
+        const double hv = 0.5 * ((double)Z[zr * lay.ldZ + zc] + (double)Z[zc * lay.ldZ + zr]);
+        aug[r * 2 * nu + c] = c < nu ? hv : (c - nu == r ? 1.0 : 0.0);
+      }
+    __syncthreads();
+    float* Gam = fp + I.oGam + (size_t)k * nu * nu;
+    if (!wg_gj_inverse<float>(nu, aug, false, perm, used, dg, Gam, nu)) return false;
+    LDS float* Gl = W;   // Gamma in LDS (nu x nu)
+    for (int r = wave(); r < nu; r += 4)
+      for (int c = lane(); c < nu; c += 64) Gl[r * nu + c] = Gam[(size_t)r * nu + c];
+    __syncthreads();
+    wg_mm_f32(nu, nx, nu, -1.f, Gl, nu, false, Z + nx * lay.ldZ, lay.ldZ, false, 0.f, Y, lay.ldY);
+    // F = [[A + B K, B], [K, I]]
+    float* Fk = fp + I.oF + (size_t)k * nxu * nxu;
+    wg_mm_f32(nx, nx, nu, 1.f, AB + nx, lay.ldAB, false, Y, lay.ldY, false, 0.f, W, lay.ldW);  // B K
+    for (int r = wave(); r < nxu; r += 4)
+      for (int c = lane(); c < nxu; c += 64) {
+        float v;
+        if (r < nx) v = c < nx ? AB[r * lay.ldAB + c] + W[r * lay.ldW + c] : AB[r * lay.ldAB + c];
+        else v = c < nx ? Y[(r - nx) * lay.ldY + c] : (c - nx == r - nx ? 1.f : 0.f);
+        Fk[(size_t)r * nxu + c] = v;
+      }
+    // ev = Abar^T P b, fv = B^T P b
+    float* ev = fp + I.oev + (size_t)k * nx;
+    float* fv = fp + I.ofv + (size_t)k * nu;
+    for (int c = tid(); c < nxu; c += kWG) {
+      float s = 0.f;
+      for (int r = 0; r < nx; ++r) {
+        const float m = c < nx ? AB[r * lay.ldAB + c] + W[r * lay.ldW + c] : AB[r * lay.ldAB + c];
+        s += m * vec[r];
+      }
+      if (c < nx) ev[c] = s; else fv[c - nx] = s;
+    }
+    // P = Z_xx + Z_ux^T K
+    for (int r = wave(); r < nx; r += 4)
+      for (int c = lane(); c < nx; c += 64) P[r * lay.ldP + c] = Z[r * lay.ldZ + c];
+    __syncthreads();
+    wg_mm_f32(nx, nx, nu, 1.f, Z + nx * lay.ldZ, lay.ldZ, true, Y, lay.ldY, false, 1.f, P, lay.ldP);
+    for (int r = wave(); r < nx; r += 4)
+      for (int c = r + 1 + lane(); c < nx; c += 64) {
+        const float s = 0.5f * (P[r * lay.ldP + c] + P[c * lay.ldP + r]);
+        P[r * lay.ldP + c] = s;
+        P[c * lay.ldP + r] = s;
+      }
+    __syncthreads();
+  }
+  return true;
+}
+
+// ADMM iterations of one instance at fixed rho.  Returns 1 solved, 2 max_iter,
+// 3 numerical, 4 rho change (new rho in *rho_new).
+__device__ int batch_iterate(const BInst& I, const BatchArgs& a, double rho, int* it, double* rho_new,
+                             double* rp_out, double* rd_out, LDS char* base) {
+  const int N = I.N, nx = I.nx, nu = I.nu, nc = I.nc, nf = I.nf, nxu = nx + nu;
+  const BLayout lay = batch_layout(nx, nu, I.box ? 0 : (nc > nf ? nc : nf));
+  LDS float* F0 = (LDS float*)base;
+  LDS float* g = F0 + lay.vec;
+  LDS float* g2 = g + kBV;
+  LDS float* xz = g2 + kBV;
+  LDS float* tv = xz + kBV;
+  LDS float* tu = tv + kBV;
+  LDS float* wv = tu + kBV;
+  LDS float* wv2 = wv + kBV;
+  LDS float* part = wv2 + 2 * kBV;
+  LDS double* red = (LDS double*)(base + lay.red);
+  float* fp = a.fp;
+  double* dp = a.dp;
+  const float fr = (float)rho;
+  double* ys = dp + I.oy;
+  double* zs = dp + I.oz;
+  double* vacc = dp + I.ov;
+  double* wprev = dp + I.owp;
+  const double* ls = dp + I.ol;
+  const double* us = dp + I.ou;
+  double* X = dp + I.oX;
+  double* U = dp + I.oU;
+  float* kff = fp + I.okff;
+  const float* x0 = fp + I.ox0;
+  double hnorm = 0.0;
+  for (int t = tid(); t < (N + 1) * nx; t += kWG) hnorm = fmax(hnorm, fabs((double)fp[I.oq + t]));
+  for (int t = tid(); t < N * nu; t += kWG) hnorm = fmax(hnorm, fabs((double)fp[I.orr + t]));
+  hnorm = wg_max_d(hnorm, red);
+  bool first = true;
+  while (true) {
+    ++*it;
+    const bool full = first;
+    const float cst = full ? 1.f : 0.f;
+    const bool sigma_it = a.adaptive && (*it % a.sigma == 0) && *it < a.max_iter;
+    // ---- backward: p_N = cst q_N + rho C_N^T dw_N
+    for (int r = tid(); r < nf; r += kWG) {
+      const size_t gr = (size_t)N * nc + r;
+      const double w = ys[gr] - zs[gr];
+      wv[r] = (float)(full ? w : w - wprev[gr]);
+      wprev[gr] = w;
+    }
+    __syncthreads();
+    if (nf > 0 && !I.box) wg_gemv_t<float, 20>(nf, nx, (const float*)(fp + I.oCN), nx, wv, tv, part, false);
+    for (int j = tid(); j < nx; j += kWG) {
+      const float cw = nf > 0 ? (I.box ? wv[j] : tv[j]) : 0.f;
+      g[j] = cst * fp[I.oq + (size_t)N * nx + j] + fr * cw;
+    }
+    __syncthreads();
+    for (int i = N - 1; i >= 0; --i) {
+      const float* Fi = fp + I.oF + (size_t)i * nxu * nxu;
+      // dw_i and [C^T w; D^T w]
+      for (int r = tid(); r < nc; r += kWG) {
+        const size_t gr = (size_t)i * nc + r;
+        const double w = ys[gr] - zs[gr];
+        wv[r] = (float)(full ? w : w - wprev[gr]);
+        wprev[gr] = w;
+      }
+      __syncthreads();
+      if (!I.box) {
+        if (nc > 0) {
+          wg_gemv_t<float, 16>(nc, nxu, (const float*)(fp + I.oG + (size_t)i * nc * nxu), nxu, wv, tv, part, false);
+        } else {
+          for (int j = tid(); j < nxu; j += kWG) tv[j] = 0.f;
+          __syncthreads();
+        }
+      }
+      // r_hat (tu), c = q_hat + ev + K^T r_hat (wv2)
+      for (int j = tid(); j < nu; j += kWG) {
+        const float gw = I.box ? wv[nx + j] : tv[nx + j];
+        tu[j] = cst * fp[I.orr + (size_t)i * nu + j] + fr * gw;
+      }
+      for (int j = tid(); j < nx; j += kWG) {
+        const float gw = I.box ? wv[j] : tv[j];
+        wv2[j] = cst * (fp[I.oq + (size_t)i * nx + j] + fp[I.oev + (size_t)i * nx + j]) + fr * gw;
+      }
+      __syncthreads();
+      wg_gemv_t<float, 8>(nu, nx, Fi + nx * nxu, nxu, tu, wv2, part, true);   // + K^T r_hat
+      // [Abar^T p; B^T p]
+      wg_gemv_t<float, 20>(nx, nxu, Fi, nxu, g, g2, part, false);
+      for (int j = tid(); j < nu; j += kWG) tu[j] = g2[nx + j] + tu[j] + cst * fp[I.ofv + (size_t)i * nu + j];
+      for (int j = tid(); j < nx; j += kWG) g[j] = g2[j] + wv2[j];
+      __syncthreads();
+      // k_i = -Gamma (B^T p + f + r_hat)
+      wg_gemv_t<float, 8>(nu, nu, (const float*)(fp + I.oGam + (size_t)i * nu * nu), nu, tu, g2, part, false);
+      for (int j = tid(); j < nu; j += kWG) kff[(size_t)i * nu + j] = -g2[j];
+      __syncthreads();
+    }
+    // ---- forward roll-out, projection, dual update, residuals
+    double rp = 0.0, rd = 0.0, vmax = 0.0, zmax = 0.0, hx = 0.0, gl = 0.0;
+    for (int j = tid(); j < nx; j += kWG) xz[j] = cst * x0[j];
+    __syncthreads();
+    for (int i = 0; i <= N; ++i) {
+      const bool term = (i == N);
+      const int nr = term ? nf : nc;
+      for (int j = tid(); j < nx; j += kWG) {
+        const size_t gi = (size_t)i * nx + j;
+        X[gi] = full ? (double)xz[j] : X[gi] + (double)xz[j];
+      }
+      if (!term) {
+        const float* Fi = fp + I.oF + (size_t)i * nxu * nxu;
+        for (int j = tid(); j < nu; j += kWG) xz[nx + j] = kff[(size_t)i * nu + j];
+        __syncthreads();
+        wg_gemv_n<float, 24>(nxu, nxu, Fi, nxu, xz, g2, part, false);   // [Abar x + B k; K x + k]
+        for (int j = tid(); j < nu; j += kWG) {
+          const float uu = g2[nx + j];
+          xz[nx + j] = uu;
+          const size_t gi = (size_t)i * nu + j;
+          U[gi] = full ? (double)uu : U[gi] + (double)uu;
+        }
+        __syncthreads();
+        if (I.box) {
+          for (int r = tid(); r < nc; r += kWG) wv[r] = xz[r];
+        } else if (nc > 0) {
+          wg_gemv_n<float, 24>(nc, nxu, (const float*)(fp + I.oG + (size_t)i * nc * nxu), nxu, xz, wv, part, false);
+        }
+      } else if (nr > 0) {
+        if (I.box) {
+          for (int r = tid(); r < nf; r += kWG) wv[r] = xz[r];
+        } else {
+          wg_gemv_n<float, 20>(nf, nx, (const float*)(fp + I.oCN), nx, xz, wv, part, false);
+        }
+      }
+      __syncthreads();
+      for (int r = tid(); r < nr; r += kWG) {
+        const size_t gr = (size_t)i * nc + r;
+        const double v = full ? (double)wv[r] : vacc[gr] + (double)wv[r];
+        vacc[gr] = v;
+        const double yo = ys[gr], zo = zs[gr];
+        const double t = v + yo;
+        const double zn = t < ls[gr] ? ls[gr] : (t > us[gr] ? us[gr] : t);
+        const double yn = yo + v - zn;
+        zs[gr] = zn;
+        ys[gr] = yn;
+        const double e = fabs(v - zn);
+        rp = (e > rp || e != e) ? e : rp;
+        vmax = fmax(vmax, fabs(v));
+        zmax = fmax(zmax, fabs(zn));
+        wv[r] = (float)(zn - zo);
+        wv2[r] = (float)yn;
+      }
+      __syncthreads();
+      if (nr > 0) {
+        if (I.box) {
+          for (int r = tid(); r < nr; r += kWG) {
+            const double q = rho * fabs((double)wv[r]);
+            rd = (q > rd || q != q) ? q : rd;
+            if (sigma_it) gl = fmax(gl, rho * fabs((double)wv2[r]));
+          }
+        } else {
+          const int ncol = term ? nx : nxu;
+          const float* Gm = term ? fp + I.oCN : fp + I.oG + (size_t)i * nc * nxu;
+          const int ldm = term ? nx : nxu;
+          wg_gemv_t<float, 16>(nr, ncol, Gm, ldm, wv, tv, part, false);
+          for (int j = tid(); j < ncol; j += kWG) {
+            const double q = rho * fabs((double)tv[j]);
+            rd = (q > rd || q != q) ? q : rd;
+          }
+          if (sigma_it) {
+            wg_gemv_t<float, 16>(nr, ncol, Gm, ldm, wv2, tv, part, false);
+            for (int j = tid(); j < ncol; j += kWG) gl = fmax(gl, rho * fabs((double)tv[j]));
+          }
+        }
+        __syncthreads();
+      }
+      if (sigma_it) {
+        // |H xi| on the accumulated iterate
+        for (int j = tid(); j < nx; j += kWG) tv[j] = (float)X[(size_t)i * nx + j];
+        if (!term)
+          for (int j = tid(); j < nu; j += kWG) tu[j] = (float)U[(size_t)i * nu + j];
+        __syncthreads();
+        wg_gemv_n<float, 20>(nx, nx, (const float*)(fp + I.oQ + (size_t)i * nx * nx), nx, tv, wv2, part, false);
+        if (!term) {
+          wg_gemv_t<float, 8>(nu, nx, (const float*)(fp + I.oS + (size_t)i * nu * nx), nx, tu, wv2, part, true);
+          wg_gemv_n<float, 8>(nu, nu, (const float*)(fp + I.oR + (size_t)i * nu * nu), nu, tu, g, part, false);
+          wg_gemv_n<float, 20>(nu, nx, (const float*)(fp + I.oS + (size_t)i * nu * nx), nx, tv, g, part, true);
+          for (int j = tid(); j < nu; j += kWG) hx = fmax(hx, fabs((double)g[j]));
+        }
+        for (int j = tid(); j < nx; j += kWG) hx = fmax(hx, fabs((double)wv2[j]));
+        __syncthreads();
+      }
+      if (term) break;
+      for (int j = tid(); j < nx; j += kWG) xz[j] = g2[j] + cst * fp[I.ob + (size_t)i * nx + j];
+      __syncthreads();
+    }
+    first = false;
+    rp = wg_max_d(rp, red);
+    rd = wg_max_d(rd, red);
+    *rp_out = rp;
+    *rd_out = rd;
+    if (rp != rp || rd != rd || isinf(rp) || isinf(rd)) return 3;
+    if (rp <= a.tol && rd <= a.tol) return 1;
+    if (*it >= a.max_iter) return 2;
+    if (sigma_it) {
+      vmax = wg_max_d(vmax, red); zmax = wg_max_d(zmax, red);
+      hx = wg_max_d(hx, red); gl = wg_max_d(gl, red);
+      const double ps = fmax(vmax, zmax), ds = fmax(fmax(hx, gl), hnorm);
+      const double ratio = (rp / (ps + 1e-10)) / (rd / (ds + 1e-10) + 1e-10);
+      double rn = fmin(fmax(rho * sqrt(ratio), a.rho_min), a.rho_max);
+      if (rn > rho * a.rho_tol || rn < rho / a.rho_tol) {
+        const double f = rho / rn;
+        for (int r = tid(); r < I.m; r += kWG) ys[r] *= f;
+        __syncthreads();
+        *rho_new = rn;
+        return 4;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kWG) k_batch(BatchArgs a) {
+  extern __shared__ __align__(16) char lds_generic[];
+  LDS char* base = (LDS char*)lds_generic;
+  __shared__ unsigned s_item;
+  while (true) {
+    if (tid() == 0) s_item = atomicAdd(a.counter, 1u);
+    __syncthreads();
+    const unsigned item = s_item;
+    __syncthreads();
+    if (item >= (unsigned)a.count) break;
+    const int idx = a.order[item];
+    const BInst I = a.inst[idx];
+    if (!a.warm[idx])
+      for (int r = tid(); r < I.m; r += kWG) { a.dp[I.oz + r] = 0.0; a.dp[I.oy + r] = 0.0; }
+    __syncthreads();
+    double rho = a.rho0[idx];
+    int it = 0, nupd = 0, nfact = 0, st = 0;
+    double rp = 0.0, rd = 0.0;
+    while (true) {
+      ++nfact;
+      if (!batch_epoch(I, a, rho, base)) { st = -1; break; }
+      double rn = rho;
+      st = batch_iterate(I, a, rho, &it, &rn, &rp, &rd, base);
+      if (st != 4) break;
+      rho = rn;
+      ++nupd;
+    }
+    if (tid() == 0) {
+      BResult r;
+      r.status = st; r.iterations = it; r.rho_updates = nupd; r.factorizations = nfact;
+      r.r_p = rp; r.r_d = rd; r.rho = rho;
+      a.res[idx] = r;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_u32(unsigned* p) { *p = 0u; }
+
+// ------------------------------------------------------------------ host
+struct BatchSolver {
+  hipStream_t stream = nullptr;
+  gsls_settings st;
+  int count = 0;
+  std::vector<BInst> inst;
+  std::vector<int> order;
+  std::vector<int> nx_of;
+  size_t nfp = 0, ndp = 0, lds = 0;
+  float* fp = nullptr;
+  double* dp = nullptr;
+  BInst* d_inst = nullptr;
+  int* d_order = nullptr;
+  double* d_rho = nullptr;
+  int* d_warm = nullptr;
+  BResult* d_res = nullptr;
+  unsigned* d_counter = nullptr;
+  int grid = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double graph_key[4] = {-1, -1, -1, -1};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~BatchSolver() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (void* p : {(void*)fp, (void*)dp, (void*)d_inst, (void*)d_order, (void*)d_rho, (void*)d_warm,
+                    (void*)d_res, (void*)d_counter})
+      if (p) (void)hipFree(p);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
+static bool is_box(const gsls_qp_desc& d, const std::vector<double>& C, const std::vector<double>& D,
+                   const std::vector<double>& CN) {
+  const int nx = d.nx, nu = d.nu, nc = d.nc, nf = d.nf;
+  if (nc != nx + nu) return false;
+  if (nf != 0 && nf != nx) return false;
+  for (int k = 0; k < d.N; ++k)
+    for (int r = 0; r < nc; ++r) {
+      for (int j = 0; j < nx; ++j)
+        if (C[((size_t)k * nc + r) * nx + j] != (r == j ? 1.0 : 0.0)) return false;
+      for (int j = 0; j < nu; ++j)
+        if (D[((size_t)k * nc + r) * nu + j] != (r == nx + j ? 1.0 : 0.0)) return false;
+    }
+  for (int r = 0; r < nf; ++r)
+    for (int j = 0; j < nx; ++j)
+      if (CN[(size_t)r * nx + j] != (r == j ? 1.0 : 0.0)) return false;
+  return true;
+}
+
+int batch_setup(const gsls_qp_desc* descs, int count, const gsls_settings* s, hipStream_t stream, BatchSolver* B) {
+  B->stream = stream;
+  B->st = *s;
+  B->count = count;
+  B->inst.resize(count);
+  std::vector<float> fpool;
+  std::vector<double> dpool;
+  auto pushf = [&](const double* p, size_t n) {
+    long long o = (long long)fpool.size();
+    for (size_t i = 0; i < n; ++i) fpool.push_back(p ? (float)p[i] : 0.f);
+    while (fpool.size() % 4) fpool.push_back(0.f);
+    return o;
+  };
+  auto reservef = [&](size_t n) {
+    long long o = (long long)fpool.size();
+    fpool.resize(fpool.size() + ((n + 3) & ~(size_t)3), 0.f);
+    return o;
+  };
+  auto pushd = [&](const double* p, size_t n) {
+    long long o = (long long)dpool.size();
+    for (size_t i = 0; i < n; ++i) dpool.push_back(p ? p[i] : 0.0);
+    while (dpool.size() % 2) dpool.push_back(0.0);
+    return o;
+  };
+  auto reserved = [&](size_t n) {
+    long long o = (long long)dpool.size();
+    dpool.resize(dpool.size() + ((n + 1) & ~(size_t)1), 0.0);
+    return o;
+  };
+  size_t lds = 0;
+  std::vector<double> cost(count);
+  for (int c = 0; c < count; ++c) {
+    const gsls_qp_desc& d = descs[c];
+    if (d.mem != GSLS_HOST) return GSLS_ERR_INVALID_ARG;
+    const size_t N = d.N, nx = d.nx, nu = d.nu, nc = d.nc, nf = d.nf, nxu = nx + nu;
+    if (nx + nu > kBatchMaxNxu) return GSLS_ERR_DIM;
+    std::vector<double> C(d.C ? d.C : (const double*)nullptr, d.C ? d.C + N * nc * nx : nullptr);
+    std::vector<double> D(d.D ? d.D : (const double*)nullptr, d.D ? d.D + N * nc * nu : nullptr);
+    std::vector<double> CN(d.CN ? d.CN : (const double*)nullptr, d.CN ? d.CN + nf * nx : nullptr);
+    BInst& I = B->inst[c];
+    I.N = d.N; I.nx = d.nx; I.nu = d.nu; I.nc = d.nc; I.nf = d.nf; I.m = (int)(N * nc + nf);
+    I.box = is_box(d, C, D, CN) ? 1 : 0;
+    // general rows go through the GEMV helpers (at most 64 reduction rows)
+    if (!I.box && (nc > (size_t)GSLS_MAX_NC || nf > (size_t)GSLS_MAX_NC)) return GSLS_ERR_DIM;
+    I.oA = pushf(d.A, N * nx * nx); I.oB = pushf(d.B, N * nx * nu); I.ob = pushf(d.b, N * nx);
+    I.oQ = pushf(d.Q, (N + 1) * nx * nx); I.oR = pushf(d.R, N * nu * nu); I.oS = pushf(d.S, N * nu * nx);
+    I.oq = pushf(d.q, (N + 1) * nx); I.orr = pushf(d.r, N * nu);
+    if (!I.box) {
+      std::vector<double> G(N * nc * nxu);
+      for (size_t k = 0; k < N; ++k)
+        for (size_t r = 0; r < nc; ++r) {
+          for (size_t j = 0; j < nx; ++j) G[(k * nc + r) * nxu + j] = C[(k * nc + r) * nx + j];
+          for (size_t j = 0; j < nu; ++j) G[(k * nc + r) * nxu + nx + j] = D[(k * nc + r) * nu + j];
+        }
+      I.oG = pushf(G.data(), G.size());
+      I.oCN = pushf(CN.data(), CN.size());
+    } else {
+      I.oG = 0; I.oCN = 0;
+    }
+    I.ox0 = reservef(nx);
+    I.oF = reservef(N * nxu * nxu); I.oGam = reservef(N * nu * nu);
+    I.oev = reservef(N * nx); I.ofv = reservef(N * nu); I.okff = reservef(N * nu);
+    I.ol = pushd(d.l, I.m); I.ou = pushd(d.u, I.m);
+    I.oz = reserved(I.m); I.oy = reserved(I.m); I.ov = reserved(I.m); I.owp = reserved(I.m);
+    I.oX = reserved((N + 1) * nx); I.oU = reserved(N * nu);
+    lds = std::max(lds, batch_layout(d.nx, d.nu, I.box ? 0 : std::max(d.nc, d.nf)).bytes);
+    cost[c] = (double)N * nxu * nxu;
+  }
+  B->order.resize(count);
+  for (int c = 0; c < count; ++c) B->order[c] = c;
+  std::stable_sort(B->order.begin(), B->order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  if (lds > kBatchLdsMax) return GSLS_ERR_DIM;
+  B->lds = lds;
+  B->nfp = fpool.size(); B->ndp = dpool.size();
+  if (hipMalloc(&B->fp, B->nfp * 4) != hipSuccess) return GSLS_ERR_OOM;
+  if (hipMalloc(&B->dp, B->ndp * 8) != hipSuccess) return GSLS_ERR_OOM;
+  if (hipMalloc(&B->d_inst, count * sizeof(BInst)) != hipSuccess) return GSLS_ERR_OOM;
+  if (hipMalloc(&B->d_order, count * sizeof(int)) != hipSuccess) return GSLS_ERR_OOM;
+  if (hipMalloc(&B->d_rho, count * sizeof(double)) != hipSuccess) return GSLS_ERR_OOM;
+  if (hipMalloc(&B->d_warm, count * sizeof(int)) != hipSuccess) return GSLS_ERR_OOM;
+  if (hipMalloc(&B->d_res, count * sizeof(BResult)) != hipSuccess) return GSLS_ERR_OOM;
+  if (hipMalloc(&B->d_counter, sizeof(unsigned)) != hipSuccess) return GSLS_ERR_OOM;
+  if (hipMemcpy(B->fp, fpool.data(), B->nfp * 4, hipMemcpyHostToDevice) != hipSuccess) return GSLS_ERR_HIP;
+  if (hipMemcpy(B->dp, dpool.data(), B->ndp * 8, hipMemcpyHostToDevice) != hipSuccess) return GSLS_ERR_HIP;
+  if (hipMemcpy(B->d_inst, B->inst.data(), count * sizeof(BInst), hipMemcpyHostToDevice) != hipSuccess)
+    return GSLS_ERR_HIP;
+  if (hipMemcpy(B->d_order, B->order.data(), count * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return GSLS_ERR_HIP;
+  if (hipFuncSetAttribute((const void*)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return GSLS_ERR_HIP;
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return GSLS_ERR_HIP;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return GSLS_ERR_HIP;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_batch, kWG, lds) != hipSuccess) per = 1;
+  B->grid = std::min(count, cus * std::max(per, 1));
+  if (hipEventCreate(&B->e0) != hipSuccess || hipEventCreate(&B->e1) != hipSuccess) return GSLS_ERR_HIP;
+  return GSLS_OK;
+}
+
+int batch_solve(BatchSolver* B, const double* const* x0, const double* rho, double tol, const double* const* z0,
+                const double* const* y0, gsls_result* out, double* ms) {
+  const int count = B->count;
+  if (!x0 || !rho || !out || !(tol >= 0)) return GSLS_ERR_INVALID_ARG;
+  std::vector<int> warm(count, 0);
+  for (int c = 0; c < count; ++c) {
+    if (!x0[c] || !(rho[c] > 0) || !std::isfinite(rho[c])) return GSLS_ERR_INVALID_ARG;
+    for (int j = 0; j < B->inst[c].nx; ++j)
+      if (!std::isfinite(x0[c][j])) return GSLS_ERR_INVALID_ARG;
+  }
+  // host staging stays alive until the stream is synchronised below
+  std::vector<float> xf;
+  std::vector<size_t> xoff(count);
+  for (int c = 0; c < count; ++c) {
+    xoff[c] = xf.size();
+    for (int j = 0; j < B->inst[c].nx; ++j) xf.push_back((float)x0[c][j]);
+  }
+  for (int c = 0; c < count; ++c) {
+    const BInst& I = B->inst[c];
+    if (hipMemcpyAsync(B->fp + I.ox0, xf.data() + xoff[c], I.nx * 4, hipMemcpyHostToDevice, B->stream) !=
+        hipSuccess)
+      return GSLS_ERR_HIP;
+    if (z0 && y0 && z0[c] && y0[c]) {
+      warm[c] = 1;
+      if (hipMemcpyAsync(B->dp + I.oz, z0[c], I.m * 8, hipMemcpyHostToDevice, B->stream) != hipSuccess)
+        return GSLS_ERR_HIP;
+      if (hipMemcpyAsync(B->dp + I.oy, y0[c], I.m * 8, hipMemcpyHostToDevice, B->stream) != hipSuccess)
+        return GSLS_ERR_HIP;
+    }
+  }
+  if (hipMemcpyAsync(B->d_rho, rho, count * 8, hipMemcpyHostToDevice, B->stream) != hipSuccess) return GSLS_ERR_HIP;
+  if (hipMemcpyAsync(B->d_warm, warm.data(), count * 4, hipMemcpyHostToDevice, B->stream) != hipSuccess)
+    return GSLS_ERR_HIP;
+  BatchArgs a{};
+  a.inst = B->d_inst; a.order = B->d_order; a.count = count; a.fp = B->fp; a.dp = B->dp; a.rho0 = B->d_rho;
+  a.tol = tol; a.max_iter = B->st.max_iter; a.adaptive = B->st.adaptive_rho; a.sigma = B->st.sigma;
+  a.rho_min = B->st.rho_min; a.rho_max = B->st.rho_max; a.rho_tol = B->st.rho_tol;
+  a.res = B->d_res; a.counter = B->d_counter; a.warm = B->d_warm;
+  // the launch (counter reset by a fill kernel, then the persistent solver) is
+  // captured once per tolerance into a graph and replayed
+  if (!B->gexec || B->graph_key[0] != tol) {
+    if (B->gexec) { (void)hipGraphExecDestroy(B->gexec); B->gexec = nullptr; }
+    if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return GSLS_ERR_HIP;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return GSLS_ERR_HIP;
+    k_zero_u32<<<1, 1, 0, cs>>>(B->d_counter);
+    k_batch<<<B->grid, kWG, B->lds, cs>>>(a);
+    if (hipStreamEndCapture(cs, &B->graph) != hipSuccess) return GSLS_ERR_HIP;
+    (void)hipStreamDestroy(cs);
+    if (hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0) != hipSuccess) return GSLS_ERR_HIP;
+    B->graph_key[0] = tol;
+  }
+  if (hipEventRecord(B->e0, B->stream) != hipSuccess) return GSLS_ERR_HIP;
+  if (hipGraphLaunch(B->gexec, B->stream) != hipSuccess) return GSLS_ERR_HIP;
+  if (hipEventRecord(B->e1, B->stream) != hipSuccess) return GSLS_ERR_HIP;
+  std::vector<BResult> res(count);
+  if (hipMemcpyAsync(res.data(), B->d_res, count * sizeof(BResult), hipMemcpyDeviceToHost, B->stream) != hipSuccess)
+    return GSLS_ERR_HIP;
+  if (hipStreamSynchronize(B->stream) != hipSuccess) return GSLS_ERR_HIP;
+  float t = 0.f;
+  (void)hipEventElapsedTime(&t, B->e0, B->e1);
+  if (ms) *ms = t;
+  int rc = GSLS_OK;
+  for (int c = 0; c < count; ++c) {
+    gsls_result r{};
+    const BResult& b = res[c];
+    if (b.status == -1) rc = GSLS_ERR_NOT_PD;
+    r.status = b.status == 1 ? GSLS_SOLVED : (b.status == 2 ? GSLS_MAX_ITER : GSLS_NUMERICAL_FAIL);
+    r.iterations = b.iterations; r.rho_updates = b.rho_updates; r.factorizations = b.factorizations;
+    r.r_p = b.r_p; r.r_d = b.r_d; r.rho = b.rho; r.ms_total = t;
+    out[c] = r;
+  }
+  return rc;
+}
+
+int batch_get(BatchSolver* B, int idx, double* X, double* U, double* z, double* lam, double rho_final) {
+  if (idx < 0 || idx >= B->count) return GSLS_ERR_INVALID_ARG;
+  const BInst& I = B->inst[idx];
+  auto cp = [&](double* dst, long long off, size_t n, double sc) -> int {
+    if (!dst) return GSLS_OK;
+    if (hipMemcpy(dst, B->dp + off, n * 8, hipMemcpyDeviceToHost) != hipSuccess) return GSLS_ERR_HIP;
+    if (sc != 1.0)
+      for (size_t i = 0; i < n; ++i) dst[i] *= sc;
+    return GSLS_OK;
+  };
+  int rc;
+  if ((rc = cp(X, I.oX, (size_t)(I.N + 1) * I.nx, 1.0))) return rc;
+  if ((rc = cp(U, I.oU, (size_t)I.N * I.nu, 1.0))) return rc;
+  if ((rc = cp(z, I.oz, I.m, 1.0))) return rc;
+  if ((rc = cp(lam, I.oy, I.m, rho_final))) return rc;
+  return GSLS_OK;
+}
+
+}  // namespace gsls
+
+// ================================================================ C ABI
+struct gsls_batch {
+  gsls::BatchSolver s;
+  std::vector<double> rho_final;
+};
+
+extern "C" {
+
+int gsls_qp_setup_batch(const gsls_qp_desc* descs, int32_t count, const gsls_settings* settings, void* stream,
+                        gsls_batch** out) {
+  if (!descs || count < 1 || !out) return GSLS_ERR_INVALID_ARG;
+  *out = nullptr;
+  gsls_settings s;
+  gsls_default_settings(&s);
+  if (settings) s = *settings;
+  if (int rc = gsls::check_settings(&s)) return rc;
+  for (int c = 0; c < count; ++c) {
+    // box rows ([x; u] per stage) may number up to nx + nu <= 96; general
+    // rows are limited in batch_setup
+    int rc = gsls::validate_host_desc(&descs[c], gsls::kBatchMaxNxu);
+    if (rc) return rc;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return GSLS_ERR_HIP;
+  gsls_batch* b = new (std::nothrow) gsls_batch;
+  if (!b) return GSLS_ERR_OOM;
+  int rc = gsls::batch_setup(descs, count, &s, (hipStream_t)stream, &b->s);
+  if (rc) { delete b; return rc; }
+  b->rho_final.assign(count, 1.0);
+  *out = b;
+  return GSLS_OK;
+}
+
+int gsls_qp_solve_batch(gsls_batch* b, const double* const* x0, const double* rho, double tol,
+                        const double* const* z0, const double* const* y0, gsls_result* out, double* ms) {
+  if (!b) return GSLS_ERR_INVALID_ARG;
+  int rc = gsls::batch_solve(&b->s, x0, rho, tol, z0, y0, out, ms);
+  if (out)
+    for (int c = 0; c < b->s.count; ++c) b->rho_final[c] = out[c].rho;
+  return rc;
+}
+
+int gsls_batch_get(gsls_batch* b, int32_t index, double* X, double* U, double* z, double* lambda) {
+  if (!b || index < 0 || index >= b->s.count) return GSLS_ERR_INVALID_ARG;
+  return gsls::batch_get(&b->s, index, X, U, z, lambda, b->rho_final[index]);
+}
+
+void gsls_batch_free(gsls_batch* b) { delete b; }
+
+}  // extern "C"

@@ -122,4 +122,9 @@ int launch_sls_beta(const SlsArgs& args, hipStream_t st);
 int launch_sls_tau(int N, int nc, int nf, const float* betaj, const float* betafj, const double* lam, double eps,
                    double* tau, hipStream_t st);
 
+// Settings check shared by the entry points; descriptor validation with a
+// row limit of max_rows per stage (host descriptors only).
+int check_settings(const gsls_settings* s);
+int validate_host_desc(const gsls_qp_desc* desc, int max_rows);
+
 }  // namespace gsls

@@ -73,6 +73,11 @@ def _load():
                                             _dp, _dp, _dp]),
         "gsls_sls_tau": (ct.c_int, [P, _dp, _dp, _dp, ct.c_double, _dp]),
         "gsls_debug_phase_cycles": (ct.c_int, [P, ct.c_int32, _dp, ct.POINTER(ct.c_int32)]),
+        "gsls_qp_setup_batch": (ct.c_int, [ct.POINTER(QPDesc), ct.c_int32, ct.POINTER(Settings), P, ct.POINTER(P)]),
+        "gsls_qp_solve_batch": (ct.c_int, [P, ct.POINTER(_dp), _dp, ct.c_double, ct.POINTER(_dp), ct.POINTER(_dp),
+                                           ct.POINTER(Result), _dp]),
+        "gsls_batch_get": (ct.c_int, [P, ct.c_int32, _dp, _dp, _dp, _dp]),
+        "gsls_batch_free": (None, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -219,3 +224,61 @@ class QP:
         if rc != OK:
             raise GslsError(rc, "gsls_sls_tau")
         return tau
+
+
+class Batch:
+    """Many QPs solved in one persistent launch (gsls_qp_setup_batch ...)."""
+
+    def __init__(self, probs, settings: Optional[Settings] = None, stream=None, **kw):
+        self.probs = list(probs)
+        self.settings = settings or default_settings(**kw)
+        descs = (QPDesc * len(self.probs))()
+        self._keep = []
+        for i, p in enumerate(self.probs):
+            d, keep = make_desc(p)
+            descs[i] = d
+            self._keep.append(keep)
+        h = ct.c_void_p()
+        rc = lib.gsls_qp_setup_batch(descs, len(self.probs), ct.byref(self.settings),
+                                     ct.c_void_p(stream) if stream else None, ct.byref(h))
+        self._keep = None
+        if rc != OK:
+            raise GslsError(rc, "gsls_qp_setup_batch")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.gsls_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def solve(self, x0s=None, rhos=1.0, tol=1e-5, z0s=None, y0s=None):
+        n = len(self.probs)
+        x0s = [_f64(p.x0) for p in self.probs] if x0s is None else [_f64(x) for x in x0s]
+        rh = _f64(np.broadcast_to(np.asarray(rhos, dtype=np.float64), (n,)).copy())
+        xp = (_dp * n)(*[_ptr(x) for x in x0s])
+        zp = yp = None
+        keep = [x0s]
+        if z0s is not None:
+            z0s = [None if z is None else _f64(z) for z in z0s]
+            y0s = [None if y is None else _f64(y) for y in y0s]
+            keep += [z0s, y0s]
+            zp = (_dp * n)(*[_ptr(z) for z in z0s])
+            yp = (_dp * n)(*[_ptr(y) for y in y0s])
+        res = (Result * n)()
+        ms = np.zeros(1)
+        rc = lib.gsls_qp_solve_batch(self.h, xp, _ptr(rh), float(tol), zp, yp, res, _ptr(ms))
+        if rc != OK:
+            raise GslsError(rc, "gsls_qp_solve_batch")
+        self.results = [r.asdict() for r in res]
+        return self.results, float(ms[0])
+
+    def get(self, i):
+        p = self.probs[i]
+        X = np.zeros((p.N + 1, p.nx)); U = np.zeros((p.N, p.nu)); z = np.zeros(p.m); lam = np.zeros(p.m)
+        rc = lib.gsls_batch_get(self.h, int(i), _ptr(X), _ptr(U), _ptr(z), _ptr(lam))
+        if rc != OK:
+            raise GslsError(rc, "gsls_batch_get")
+        return dict(X=X, U=U, z=z, lam=lam)

@@ -133,6 +133,81 @@ def bench_sls(args):
     print(json.dumps(line), flush=True)
 
 
+def batch_floor_bytes(p):
+    """Floor bytes of one cached iteration of a batch instance: as floor_bytes,
+    without the constraint matrices when the rows are the plain box [x; u]
+    (the batched kernel then applies G = I structurally)."""
+    N, nx, nu, nc, nf = p.N, p.nx, p.nu, p.nc, p.nf
+    box = p.meta.get("kind") in ("uneven", "box_lq")
+    rows = 0 if box else N * nc * (nx + nu) + nf * nx
+    return 4 * (N * (2 * nx * nx + 3 * nx * nu + nu * nu) + rows)
+
+
+def bench_batch(args):
+    """512 box-constrained QPs of uneven shape (nx in {12,36,61,75}, nu in
+    {4,12,19}, N ~ U{16..512}) in one graph-replayed persistent launch."""
+    import torch
+    from paper_2604_07644_amd import gsls, workloads as W
+    count = 512
+    probs = W.uneven_batch(count=count)
+    b = gsls.Batch(probs, stream=torch.cuda.current_stream().cuda_stream)
+    for _ in range(args.warmup):
+        b.solve(tol=TOL)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dev_ms, last = [], None
+    for _ in range(args.steps):
+        last, ms = b.solve(tol=TOL)
+        dev_ms.append(ms)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b.close()
+    iters = np.array([r["iterations"] for r in last])
+    ok = all(r["status"] == gsls.SOLVED for r in last)
+    byts = float(sum(batch_floor_bytes(p) * it for p, it in zip(probs, iters)))
+    ms = float(np.mean(dev_ms))
+    achieved = byts / (ms * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": count * args.steps / wall, "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic (seeded generator)",
+        "config": {"workload": "batch of 512 box-constrained QPs, nx in {12,36,61,75}, nu in {4,12,19}, "
+                               "N ~ U{16..512}, one graph-replayed persistent launch",
+                   "tol": TOL, "start": "cold", "all_solved": ok, "iterations_mean": float(iters.mean()),
+                   "iterations_max": int(iters.max()), "device_ms_per_batch": ms},
+        "roofline": {"kernel": "k_batch (persistent batched ADMM)", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "floor_bytes_per_batch": byts, "avg_launch_ms": ms},
+    }
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            oracle.qp_solve(probs[n], rho=1.0, tol=TOL)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_budget or n >= count:
+                break
+        line["cpu_baseline"] = {"value": n / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
+                                "sample": f"the first {n} instances of the batch, cold start, tol {TOL:g}"}
+    print(json.dumps(line), flush=True)
+
+
+def copy_calibration(mib=256, reps=3):
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters: each launch reads and writes mib MiB."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_kib_per_launch": mib * 1024, "launches": reps}), flush=True)
+
+
 def cpu_baseline(p, budget_s=10.0):
     import oracle
     t0 = time.perf_counter()
@@ -160,13 +235,24 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--with-copy", action="store_true",
+                    help="run the 256 MiB copy calibration before the benchmark, in the same process")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
+    if args.copy_calibration or args.with_copy:
+        copy_calibration()
+        if args.copy_calibration:
+            return
     if args.workload == "sls":
         bench_sls(args)
+        return
+    if args.workload == "batch":
+        bench_batch(args)
         return
 
     import torch

@@ -269,3 +269,27 @@ def random_small(N, nx, nu, nc, nf, seed, general=True, b_nonzero=True, s_nonzer
         hi[(k > 0.9)] = INF
     return QPProblem(N, nx, nu, nc, nf, A, B, b, Q, R, S, q, r, C, D, CN, lo, hi, x0,
                      meta=dict(kind="random_small", seed=seed))
+
+
+# ------------------------------------------------------ learned warm start
+WS_SIZES = (160, 512, 512, 512, 192)
+
+
+def ws_sketch(seed=7):
+    """Fixed random projection (64 x 94, entries N(0, 1/94)) of the 94-slot
+    linearisation vector of a stage onto the 64-d sketch."""
+    rng = np.random.default_rng([5, seed])
+    return rng.standard_normal((64, 94)) / np.sqrt(94.0)
+
+
+def ws_init(seed=0, sizes=WS_SIZES):
+    """Initial MLP parameters as one flat float64 vector (W1, b1, W2, b2, ...;
+    W row-major d_in x d_out): weights U[-sqrt(6/d_in), sqrt(6/d_in)] (He
+    uniform, for ReLU layers), biases 0."""
+    rng = np.random.default_rng([6, seed])
+    parts = []
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        lim = np.sqrt(6.0 / a)
+        parts.append(rng.uniform(-lim, lim, a * b))
+        parts.append(np.zeros(b))
+    return np.concatenate(parts)

@@ -109,6 +109,10 @@ typedef struct gsls_result {
   double ms_total;       /* device time of the whole solve (HIP events)           */
   double ms_factor;      /* device time spent in factor epochs                    */
   double ms_iterate;     /* device time spent in the ADMM iteration kernel        */
+  int32_t cold_restart;  /* batched learned warm start: 1 if the instance did not
+                            converge within the warm budget and was re-solved
+                            from a cold start (its iterations include both)    */
+  int32_t reserved;
 } gsls_result;
 
 typedef struct gsls_qp gsls_qp;
@@ -225,6 +229,84 @@ int gsls_qp_solve_batch(gsls_batch* b, const double* const* x0, const double* rh
 int gsls_batch_get(gsls_batch* b, int32_t index, double* X, double* U, double* z, double* lambda);
 
 void gsls_batch_free(gsls_batch* b);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start of the batched solver (an extension of the ADMM start of
+ * Sec. IV-A: the iterations begin from a predicted (z, lambda) and rho instead
+ * of z = y = 0, rho = 1).  Box-constrained instances only (rows [x_k; u_k] per
+ * stage, terminal rows x_N or none; nx <= 75, nu <= 19).
+ *
+ * One feature row per stage k = 0..N of each instance, d_in = 160, BF16:
+ *   [0:nx] x0 / x_max; [75] x_max / 5; [76] u_max; [77:141] S d_k with
+ *   d_k = [(A_k - I) x0 in slots 0..nx-1 ; B_k^T x0 in slots 75..75+nu-1] / x_max
+ *   (d_N = 0) and S the 64 x 94 sketch; [141] k/N; [142] N/512; [143] nx/75;
+ *   [144] nu/19; the rest 0.  x_max, u_max: upper bounds of the first state
+ *   row and the first input row.
+ * One output row, d_out = 192, FP32: z of the state rows / x_max in [0:nx],
+ *   of the input rows / u_max in [75:75+nu]; lambda of the state rows in
+ *   [94:94+nx], of the input rows in [169:169+nu]; log10 rho in [188].
+ * MLP 160-512-512-512-192, ReLU on the hidden layers; parameters are one flat
+ * FP32 vector W1 (160 x 512 row-major), b1, W2, b2, W3, b3, W4, b4; BF16
+ * copies feed the matrix cores (FP32 accumulation); Adam keeps FP32 master
+ * weights.  Loss sum(M (Y - T)^2) / sum(M).
+ *
+ * Device pointers (X, T, M, idx, Y) are device memory; work runs on the
+ * handle's stream (gsls_ws_create) or the batch's stream (batch calls).
+ * ------------------------------------------------------------------------ */
+typedef struct gsls_ws gsls_ws;
+
+/* Number of MLP parameters (706,240). */
+int64_t gsls_ws_nparams(void);
+
+/* New model from host params[gsls_ws_nparams()] and sketch[64 * 94] (both
+ * FP32, copied).  Adam state starts at zero. */
+int gsls_ws_create(const float* params, const float* sketch, void* stream, gsls_ws** out);
+
+/* Current FP32 master parameters into host params[gsls_ws_nparams()]. */
+int gsls_ws_get_params(gsls_ws* h, float* params);
+
+/* Binary file: 8-byte tag, int64 parameter count, FP32 parameters, FP32
+ * sketch.  Load rejects files of another layout with GSLS_ERR_INVALID_ARG. */
+int gsls_ws_save(gsls_ws* h, const char* path);
+int gsls_ws_load(const char* path, void* stream, gsls_ws** out);
+
+/* Y[rows][192] (device FP32) = MLP(X[rows][160]) (device BF16 bit patterns). */
+int gsls_ws_forward(gsls_ws* h, const uint16_t* X, int32_t rows, float* Y);
+
+/* Loss and gradient on rows idx[0..rows) of (X, T, M) (idx NULL: the first
+ * rows rows): T, M device FP32 [*][192].  grad: host FP32 [nparams] or NULL;
+ * loss: host or NULL.  No update. */
+int gsls_ws_loss_grad(gsls_ws* h, const uint16_t* X, const float* T, const float* M, const int32_t* idx,
+                      int32_t rows, float* grad, float* loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+ * gradient of those rows.  loss (host, nullable) synchronises to report it. */
+int gsls_ws_train_step(gsls_ws* h, const uint16_t* X, const float* T, const float* M, const int32_t* idx,
+                       int32_t rows, float lr, float* loss);
+
+/* Number of feature rows of a batch: sum over instances of N + 1; instance c
+ * owns a contiguous block of rows in batch order, stage k at offset k. */
+int32_t gsls_ws_batch_rows(gsls_batch* b);
+
+/* Feature rows of a batch for initial states x0 (host, NULL: the last ones
+ * uploaded) into device X[rows][160]. */
+int gsls_ws_features(gsls_ws* h, gsls_batch* b, const double* const* x0, uint16_t* X);
+
+/* Target rows and mask (device FP32 [rows][192]) from the batch's last
+ * solution: z, lambda = rho y and log10 of each instance's final rho. */
+int gsls_ws_targets(gsls_batch* b, float* T, float* M);
+
+/* Learned warm start + batched solve: features, MLP, start (rho0 =
+ * 10^(mean of the rho column over the instance's rows) clamped to the
+ * settings' [rho_min, rho_max]; z0 = prediction projected onto [l, u];
+ * y0 = predicted lambda / rho0), then the persistent solve.  An instance not
+ * converged after warm_budget iterations (0: no limit) restarts cold (z = y =
+ * 0, rho = 1) and reports cold_restart = 1.  *ms: device time of prediction
+ * and solve; *ms_predict (nullable): of the prediction alone. */
+int gsls_qp_solve_batch_ws(gsls_batch* b, gsls_ws* h, const double* const* x0, double tol, int32_t warm_budget,
+                           gsls_result* out, double* ms, double* ms_predict);
+
+void gsls_ws_free(gsls_ws* h);
 
 #ifdef __cplusplus
 }

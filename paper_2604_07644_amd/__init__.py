@@ -6,6 +6,14 @@ same scan backend.
 
 The compute runs in hand-written HIP kernels behind the C ABI of
 ``include/gsls.h`` (``libgsls.so``); ``gsls`` is a thin ctypes binding with the
-same names.  ``workloads`` holds the seeded synthetic problem generators.
+same names (imported on first use: ``from paper_2604_07644_amd import gsls``
+loads the library and raises ImportError if it is not built).  ``workloads``
+holds the seeded synthetic problem generators (numpy only).
 """
-from . import gsls  # noqa: F401
+import importlib
+
+
+def __getattr__(name):
+    if name == "gsls":
+        return importlib.import_module(".gsls", __name__)
+    raise AttributeError(name)

@@ -25,35 +25,9 @@
 
 #include "dev_common.hpp"
 #include "solver.hpp"
+#include "batch.hpp"
 
 namespace gsls {
-
-struct BInst {
-  int N, nx, nu, nc, nf, box, m;
-  long long oA, oB, ob, oQ, oR, oS, oq, orr, oG, oCN, ox0;  // float pool: problem
-  long long oF, oGam, oev, ofv, okff;                      // float pool: epoch outputs, gains
-  long long ol, ou, oz, oy, ov, owp, oX, oU;                // double pool
-};
-
-struct BResult {
-  int status, iterations, rho_updates, factorizations;
-  double r_p, r_d, rho;
-};
-
-struct BatchArgs {
-  const BInst* inst;
-  const int* order;            // instance order (largest first)
-  int count;
-  float* fp;                   // float pool
-  double* dp;                  // double pool
-  const double* rho0;          // [count]
-  double tol;
-  int max_iter, adaptive, sigma;
-  double rho_min, rho_max, rho_tol;
-  BResult* res;                // [count]
-  unsigned* counter;
-  int* warm;                   // [count] 1: start from the given z, y
-};
 
 constexpr int kBV = 128;       // work-vector length (>= nx + nu, >= nc)
 constexpr int kBatchMaxNxu = 96;
@@ -75,7 +49,7 @@ __host__ __device__ inline BLayout batch_layout(int nx, int nu, int nc) {
   L.ldP = bodd(nx); L.ldW = bodd(nxu); L.ldZ = bodd(nxu); L.ldAB = bodd(nxu); L.ldG = bodd(nxu);
   L.ldY = bodd(nx);
   auto r4 = [](size_t v) { return (v + 3) & ~(size_t)3; };
-  const size_t aug_d = (size_t)2 * nu * nu, dg_d = 32, red_d = kWG, perm_d = 32;
+  const size_t aug_d = (size_t)nu * (2 * nu + nx), dg_d = 32, red_d = kWG, perm_d = 32;
   const size_t wfl = r4((size_t)(nx > nc ? nx : nc) * L.ldW);
   const size_t afl = 2 * (aug_d + dg_d + red_d + perm_d);
   size_t o = 0;
@@ -186,21 +160,23 @@ __device__ bool batch_epoch(const BInst& I, const BatchArgs& a, double rho, LDS 
     __syncthreads();
     wg_mm_f32(nxu, nxu, nx, 1.f, AB, lay.ldAB, true, W, lay.ldW, false, 1.f, Z, lay.ldZ);
     if (!I.box && nc > 0) wg_mm_f32(nxu, nxu, nc, fr, G, lay.ldG, true, G, lay.ldG, false, 1.f, Z, lay.ldZ);
-    // Gamma = Z_uu^{-1} (FP64), K = -Gamma Z_ux
+    // [K | Gamma] = [-Z_uu^{-1} Z_ux | Z_uu^{-1}] by FP64 elimination of
+    // [Z_uu | Z_ux | I]: K comes from the elimination itself, not from a
+    // rounded Gamma (which would carry cond(Z_uu) times its rounding into P)
+    const int lda = 2 * nu + nx;
     for (int r = wave(); r < nu; r += 4)
-      for (int c = lane(); c < 2 * nu; c += 64) {
-        const int zr = nx + r, zc = nx + (c < nu ? c : 0);
-        const double hv = 0.5 * ((double)Z[zr * lay.ldZ + zc] + (double)Z[zc * lay.ldZ + zr]);
-        aug[r * 2 * nu + c] = c < nu ? hv : (c - nu == r ? 1.0 : 0.0);
+      for (int c = lane(); c < lda; c += 64) {
+        double v;
+        if (c < nu) v = 0.5 * ((double)Z[(nx + r) * lay.ldZ + nx + c] + (double)Z[(nx + c) * lay.ldZ + nx + r]);
+        else if (c < nu + nx) v = (double)Z[(nx + r) * lay.ldZ + (c - nu)];
+        else v = (c - nu - nx == r) ? 1.0 : 0.0;
+        aug[r * lda + c] = v;
       }
     __syncthreads();
     float* Gam = fp + I.oGam + (size_t)k * nu * nu;
-    if (!wg_gj_inverse<float>(nu, aug, false, perm, used, dg, Gam, nu)) return false;
-    LDS float* Gl = W;   // Gamma in LDS (nu x nu)
-    for (int r = wave(); r < nu; r += 4)
-      for (int c = lane(); c < nu; c += 64) Gl[r * nu + c] = Gam[(size_t)r * nu + c];
-    __syncthreads();
-    wg_mm_f32(nu, nx, nu, -1.f, Gl, nu, false, Z + nx * lay.ldZ, lay.ldZ, false, 0.f, Y, lay.ldY);
+    if (!wg_gj_eliminate(nu, lda, aug, false, perm, used, dg)) return false;
+    wg_gj_extract<float>(nu, lda, aug, perm, dg, 0, nx, -1.0, (float*)Y, lay.ldY);
+    wg_gj_extract<float>(nu, lda, aug, perm, dg, nx, nu, 1.0, Gam, nu);
     // F = [[A + B K, B], [K, I]]
     float* Fk = fp + I.oF + (size_t)k * nxu * nxu;
     wg_mm_f32(nx, nx, nu, 1.f, AB + nx, lay.ldAB, false, Y, lay.ldY, false, 0.f, W, lay.ldW);  // B K
@@ -240,8 +216,10 @@ __device__ bool batch_epoch(const BInst& I, const BatchArgs& a, double rho, LDS 
 
 // ADMM iterations of one instance at fixed rho.  Returns 1 solved, 2 max_iter,
 // 3 numerical, 4 rho change (new rho in *rho_new).
-__device__ int batch_iterate(const BInst& I, const BatchArgs& a, double rho, int* it, double* rho_new,
-                             double* rp_out, double* rd_out, LDS char* base) {
+// it0: iteration count when this attempt (cold or warm start) began; the rho
+// rule runs every sigma iterations of the attempt.
+__device__ int batch_iterate(const BInst& I, const BatchArgs& a, double rho, int it0, int max_iter, int* it,
+                             double* rho_new, double* rp_out, double* rd_out, LDS char* base) {
   const int N = I.N, nx = I.nx, nu = I.nu, nc = I.nc, nf = I.nf, nxu = nx + nu;
   const BLayout lay = batch_layout(nx, nu, I.box ? 0 : (nc > nf ? nc : nf));
   LDS float* F0 = (LDS float*)base;
@@ -276,7 +254,7 @@ __device__ int batch_iterate(const BInst& I, const BatchArgs& a, double rho, int
     ++*it;
     const bool full = first;
     const float cst = full ? 1.f : 0.f;
-    const bool sigma_it = a.adaptive && (*it % a.sigma == 0) && *it < a.max_iter;
+    const bool sigma_it = a.adaptive && ((*it - it0) % a.sigma == 0) && *it < max_iter;
     // ---- backward: p_N = cst q_N + rho C_N^T dw_N
     for (int r = tid(); r < nf; r += kWG) {
       const size_t gr = (size_t)N * nc + r;
@@ -434,7 +412,7 @@ __device__ int batch_iterate(const BInst& I, const BatchArgs& a, double rho, int
     *rd_out = rd;
     if (rp != rp || rd != rd || isinf(rp) || isinf(rd)) return 3;
     if (rp <= a.tol && rd <= a.tol) return 1;
-    if (*it >= a.max_iter) return 2;
+    if (*it >= max_iter) return 2;
     if (sigma_it) {
       vmax = wg_max_d(vmax, red); zmax = wg_max_d(zmax, red);
       hx = wg_max_d(hx, red); gl = wg_max_d(gl, red);
@@ -464,24 +442,39 @@ __global__ void __launch_bounds__(kWG) k_batch(BatchArgs a) {
     if (item >= (unsigned)a.count) break;
     const int idx = a.order[item];
     const BInst I = a.inst[idx];
-    if (!a.warm[idx])
+    bool warm = a.warm[idx] != 0;
+    if (!warm)
       for (int r = tid(); r < I.m; r += kWG) { a.dp[I.oz + r] = 0.0; a.dp[I.oy + r] = 0.0; }
     __syncthreads();
     double rho = a.rho0[idx];
-    int it = 0, nupd = 0, nfact = 0, st = 0;
+    int it = 0, nupd = 0, nfact = 0, st = 0, restarted = 0;
     double rp = 0.0, rd = 0.0;
+    const bool budgeted = warm && a.warm_budget > 0 && a.warm_budget < a.max_iter;
+    int limit = budgeted ? a.warm_budget : a.max_iter, it0 = 0;
     while (true) {
       ++nfact;
       if (!batch_epoch(I, a, rho, base)) { st = -1; break; }
       double rn = rho;
-      st = batch_iterate(I, a, rho, &it, &rn, &rp, &rd, base);
-      if (st != 4) break;
-      rho = rn;
-      ++nupd;
+      st = batch_iterate(I, a, rho, it0, limit, &it, &rn, &rp, &rd, base);
+      if (st == 4) { rho = rn; ++nupd; continue; }
+      if (warm && budgeted && (st == 2 || st == 3)) {
+        // the warm start did not pay off: restart from z = y = 0 with a
+        // full iteration budget of its own
+        warm = false;
+        restarted = 1;
+        it0 = it;
+        limit = it + a.max_iter;
+        rho = a.rho_cold;
+        for (int r = tid(); r < I.m; r += kWG) { a.dp[I.oz + r] = 0.0; a.dp[I.oy + r] = 0.0; }
+        __syncthreads();
+        continue;
+      }
+      break;
     }
     if (tid() == 0) {
       BResult r;
       r.status = st; r.iterations = it; r.rho_updates = nupd; r.factorizations = nfact;
+      r.restarted = restarted;
       r.r_p = rp; r.r_d = rd; r.rho = rho;
       a.res[idx] = r;
     }
@@ -492,38 +485,6 @@ __global__ void __launch_bounds__(kWG) k_batch(BatchArgs a) {
 __global__ void k_zero_u32(unsigned* p) { *p = 0u; }
 
 // ------------------------------------------------------------------ host
-struct BatchSolver {
-  hipStream_t stream = nullptr;
-  gsls_settings st;
-  int count = 0;
-  std::vector<BInst> inst;
-  std::vector<int> order;
-  std::vector<int> nx_of;
-  size_t nfp = 0, ndp = 0, lds = 0;
-  float* fp = nullptr;
-  double* dp = nullptr;
-  BInst* d_inst = nullptr;
-  int* d_order = nullptr;
-  double* d_rho = nullptr;
-  int* d_warm = nullptr;
-  BResult* d_res = nullptr;
-  unsigned* d_counter = nullptr;
-  int grid = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  double graph_key[4] = {-1, -1, -1, -1};
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  ~BatchSolver() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    for (void* p : {(void*)fp, (void*)dp, (void*)d_inst, (void*)d_order, (void*)d_rho, (void*)d_warm,
-                    (void*)d_res, (void*)d_counter})
-      if (p) (void)hipFree(p);
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-  }
-};
-
 static bool is_box(const gsls_qp_desc& d, const std::vector<double>& C, const std::vector<double>& D,
                    const std::vector<double>& CN) {
   const int nx = d.nx, nu = d.nu, nc = d.nc, nf = d.nf;
@@ -638,20 +599,31 @@ int batch_setup(const gsls_qp_desc* descs, int count, const gsls_settings* s, hi
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_batch, kWG, lds) != hipSuccess) per = 1;
   B->grid = std::min(count, cus * std::max(per, 1));
   if (hipEventCreate(&B->e0) != hipSuccess || hipEventCreate(&B->e1) != hipSuccess) return GSLS_ERR_HIP;
+  B->row_off.assign(count + 1, 0);
+  for (int c = 0; c < count; ++c) B->row_off[c + 1] = B->row_off[c] + B->inst[c].N + 1;
+  const int rows = B->row_off[count];
+  std::vector<int> row_inst(rows);
+  for (int c = 0; c < count; ++c)
+    for (int r = B->row_off[c]; r < B->row_off[c + 1]; ++r) row_inst[r] = c;
+  if (hipMalloc(&B->d_row_inst, rows * sizeof(int)) != hipSuccess) return GSLS_ERR_OOM;
+  if (hipMalloc(&B->d_row_off, (count + 1) * sizeof(int)) != hipSuccess) return GSLS_ERR_OOM;
+  if (hipMemcpy(B->d_row_inst, row_inst.data(), rows * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return GSLS_ERR_HIP;
+  if (hipMemcpy(B->d_row_off, B->row_off.data(), (count + 1) * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return GSLS_ERR_HIP;
   return GSLS_OK;
 }
 
-int batch_solve(BatchSolver* B, const double* const* x0, const double* rho, double tol, const double* const* z0,
-                const double* const* y0, gsls_result* out, double* ms) {
+int batch_upload_x0(BatchSolver* B, const double* const* x0) {
   const int count = B->count;
-  if (!x0 || !rho || !out || !(tol >= 0)) return GSLS_ERR_INVALID_ARG;
-  std::vector<int> warm(count, 0);
+  if (!x0) return GSLS_ERR_INVALID_ARG;
   for (int c = 0; c < count; ++c) {
-    if (!x0[c] || !(rho[c] > 0) || !std::isfinite(rho[c])) return GSLS_ERR_INVALID_ARG;
+    if (!x0[c]) return GSLS_ERR_INVALID_ARG;
     for (int j = 0; j < B->inst[c].nx; ++j)
       if (!std::isfinite(x0[c][j])) return GSLS_ERR_INVALID_ARG;
   }
-  // host staging stays alive until the stream is synchronised below
+  // host staging in pinned-free pageable memory: the copies are synchronous
+  // with respect to the host before this function returns
   std::vector<float> xf;
   std::vector<size_t> xoff(count);
   for (int c = 0; c < count; ++c) {
@@ -663,25 +635,22 @@ int batch_solve(BatchSolver* B, const double* const* x0, const double* rho, doub
     if (hipMemcpyAsync(B->fp + I.ox0, xf.data() + xoff[c], I.nx * 4, hipMemcpyHostToDevice, B->stream) !=
         hipSuccess)
       return GSLS_ERR_HIP;
-    if (z0 && y0 && z0[c] && y0[c]) {
-      warm[c] = 1;
-      if (hipMemcpyAsync(B->dp + I.oz, z0[c], I.m * 8, hipMemcpyHostToDevice, B->stream) != hipSuccess)
-        return GSLS_ERR_HIP;
-      if (hipMemcpyAsync(B->dp + I.oy, y0[c], I.m * 8, hipMemcpyHostToDevice, B->stream) != hipSuccess)
-        return GSLS_ERR_HIP;
-    }
   }
-  if (hipMemcpyAsync(B->d_rho, rho, count * 8, hipMemcpyHostToDevice, B->stream) != hipSuccess) return GSLS_ERR_HIP;
-  if (hipMemcpyAsync(B->d_warm, warm.data(), count * 4, hipMemcpyHostToDevice, B->stream) != hipSuccess)
-    return GSLS_ERR_HIP;
+  if (hipStreamSynchronize(B->stream) != hipSuccess) return GSLS_ERR_HIP;
+  return GSLS_OK;
+}
+
+int batch_run(BatchSolver* B, double tol, int warm_budget, gsls_result* out, double* ms) {
+  const int count = B->count;
   BatchArgs a{};
   a.inst = B->d_inst; a.order = B->d_order; a.count = count; a.fp = B->fp; a.dp = B->dp; a.rho0 = B->d_rho;
   a.tol = tol; a.max_iter = B->st.max_iter; a.adaptive = B->st.adaptive_rho; a.sigma = B->st.sigma;
   a.rho_min = B->st.rho_min; a.rho_max = B->st.rho_max; a.rho_tol = B->st.rho_tol;
   a.res = B->d_res; a.counter = B->d_counter; a.warm = B->d_warm;
+  a.warm_budget = warm_budget; a.rho_cold = 1.0;
   // the launch (counter reset by a fill kernel, then the persistent solver) is
-  // captured once per tolerance into a graph and replayed
-  if (!B->gexec || B->graph_key[0] != tol) {
+  // captured once per (tol, warm budget) into a graph and replayed
+  if (!B->gexec || B->graph_key[0] != tol || B->graph_key[1] != (double)warm_budget) {
     if (B->gexec) { (void)hipGraphExecDestroy(B->gexec); B->gexec = nullptr; }
     if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
     hipStream_t cs;
@@ -693,6 +662,7 @@ int batch_solve(BatchSolver* B, const double* const* x0, const double* rho, doub
     (void)hipStreamDestroy(cs);
     if (hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0) != hipSuccess) return GSLS_ERR_HIP;
     B->graph_key[0] = tol;
+    B->graph_key[1] = (double)warm_budget;
   }
   if (hipEventRecord(B->e0, B->stream) != hipSuccess) return GSLS_ERR_HIP;
   if (hipGraphLaunch(B->gexec, B->stream) != hipSuccess) return GSLS_ERR_HIP;
@@ -712,9 +682,35 @@ int batch_solve(BatchSolver* B, const double* const* x0, const double* rho, doub
     r.status = b.status == 1 ? GSLS_SOLVED : (b.status == 2 ? GSLS_MAX_ITER : GSLS_NUMERICAL_FAIL);
     r.iterations = b.iterations; r.rho_updates = b.rho_updates; r.factorizations = b.factorizations;
     r.r_p = b.r_p; r.r_d = b.r_d; r.rho = b.rho; r.ms_total = t;
+    r.cold_restart = b.restarted;
     out[c] = r;
   }
   return rc;
+}
+
+int batch_solve(BatchSolver* B, const double* const* x0, const double* rho, double tol, const double* const* z0,
+                const double* const* y0, gsls_result* out, double* ms) {
+  const int count = B->count;
+  if (!x0 || !rho || !out || !(tol >= 0)) return GSLS_ERR_INVALID_ARG;
+  for (int c = 0; c < count; ++c)
+    if (!(rho[c] > 0) || !std::isfinite(rho[c])) return GSLS_ERR_INVALID_ARG;
+  int rc = batch_upload_x0(B, x0);
+  if (rc) return rc;
+  std::vector<int> warm(count, 0);
+  for (int c = 0; c < count; ++c) {
+    const BInst& I = B->inst[c];
+    if (z0 && y0 && z0[c] && y0[c]) {
+      warm[c] = 1;
+      if (hipMemcpyAsync(B->dp + I.oz, z0[c], I.m * 8, hipMemcpyHostToDevice, B->stream) != hipSuccess)
+        return GSLS_ERR_HIP;
+      if (hipMemcpyAsync(B->dp + I.oy, y0[c], I.m * 8, hipMemcpyHostToDevice, B->stream) != hipSuccess)
+        return GSLS_ERR_HIP;
+    }
+  }
+  if (hipMemcpyAsync(B->d_rho, rho, count * 8, hipMemcpyHostToDevice, B->stream) != hipSuccess) return GSLS_ERR_HIP;
+  if (hipMemcpyAsync(B->d_warm, warm.data(), count * 4, hipMemcpyHostToDevice, B->stream) != hipSuccess)
+    return GSLS_ERR_HIP;
+  return batch_run(B, tol, 0, out, ms);
 }
 
 int batch_get(BatchSolver* B, int idx, double* X, double* U, double* z, double* lam, double rho_final) {
@@ -738,11 +734,6 @@ int batch_get(BatchSolver* B, int idx, double* X, double* U, double* z, double* 
 }  // namespace gsls
 
 // ================================================================ C ABI
-struct gsls_batch {
-  gsls::BatchSolver s;
-  std::vector<double> rho_final;
-};
-
 extern "C" {
 
 int gsls_qp_setup_batch(const gsls_qp_desc* descs, int32_t count, const gsls_settings* settings, void* stream,

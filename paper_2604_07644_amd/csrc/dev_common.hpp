@@ -211,22 +211,20 @@ __device__ inline void wg_row_norms(int m, int n, const LDS float* M, int ld, in
 
 // -------------------------------------------------- FP64 Gauss-Jordan inverse
 constexpr int kGJRows = kMaxNx / 4;   // rows per wave
-// Inverse of the n x n matrix held in the left half of Aug = [M | I] (LDS,
-// FP64, n x 2n row-major, the caller fills both halves).  Column j's pivot is
-// the largest |entry| among rows not used as pivots yet (pivot = true), or
-// simply row j (pivot = false: for symmetric positive definite M, where every
-// pivot must then be positive; a non-positive pivot is reported as failure).
-// Rows are never swapped: perm[j] records the pivot row of column j, and the
-// pivot rows are normalised at the end (elimination and row scaling commute).
-// On return Minv[j][c] = Aug[perm[j]][n + c] / dg[j] is written to Minv (ldm),
-// converted to TO.  Two barriers per column.  Returns false uniformly on a
-// zero, negative (SPD mode) or non-finite pivot.
-// used: LDS int[n]; perm: LDS int[n]; dg: LDS double[n].
-template <typename TO>
-__device__ inline bool wg_gj_inverse(int n, LDS double* Aug, bool pivot, LDS int* perm, LDS int* used,
-                                     LDS double* dg, TO* Minv, int ldm) {
+// Gauss-Jordan elimination of Aug = [M | R] (LDS, FP64, n x ld row-major,
+// ld = n + r, the caller fills both parts): on success the right part holds
+// M^{-1} R up to the row permutation perm and the row scales 1/dg, i.e.
+// (M^{-1} R)[j][c] = Aug[perm[j]][n + c] / dg[j] (read with wg_gj_extract).
+// Column j's pivot is the largest |entry| among rows not used as pivots yet
+// (pivot = true), or simply row j (pivot = false: for symmetric positive
+// definite M, where every pivot must then be positive; a non-positive pivot
+// is reported as failure).  Rows are never swapped and the pivot rows are
+// normalised at the end (elimination and row scaling commute).  Two barriers
+// per column.  Returns false uniformly on a zero, negative (SPD mode) or
+// non-finite pivot.  used: LDS int[n]; perm: LDS int[n]; dg: LDS double[n].
+__device__ inline bool wg_gj_eliminate(int n, int ld, LDS double* Aug, bool pivot, LDS int* perm, LDS int* used,
+                                       LDS double* dg) {
   __shared__ int s_piv, s_bad;
-  const int ld = 2 * n;
   const int lane = tid() & 63, w = tid() >> 6;
   for (int r = tid(); r < n; r += kWG) used[r] = 0;
   if (tid() == 0) s_bad = 0;
@@ -261,7 +259,7 @@ __device__ inline bool wg_gj_inverse(int n, LDS double* Aug, bool pivot, LDS int
     const int p = s_piv;
     const double inv = 1.0 / Aug[p * ld + j];
     const LDS double* prow = Aug + p * ld;
-    // eliminate column j from every other row (columns > j of both halves):
+    // eliminate column j from every other row (columns > j of both parts):
     // the wave's multipliers, then per 64-column slot all its rows' entries,
     // are loaded before any is updated, so LDS latency is paid once per slot
     double mult[kGJRows];
@@ -286,12 +284,29 @@ __device__ inline bool wg_gj_inverse(int n, LDS double* Aug, bool pivot, LDS int
   }
   for (int j = tid(); j < n; j += kWG) dg[j] = 1.0 / Aug[perm[j] * ld + j];
   __syncthreads();
+  return true;
+}
+
+// Out[j][c] = scale * (M^{-1} R)[j][c0 + c] for c < m, after wg_gj_eliminate,
+// converted to TO (any memory, leading dimension ldo).  Ends with a barrier.
+template <typename TO>
+__device__ inline void wg_gj_extract(int n, int ld, const LDS double* Aug, const LDS int* perm,
+                                     const LDS double* dg, int c0, int m, double scale, TO* Out, int ldo) {
+  const int lane = tid() & 63, w = tid() >> 6;
   for (int r = w; r < n; r += 4) {
-    const LDS double* row = Aug + perm[r] * ld + n;
-    const double sc = dg[r];
-    for (int c = lane; c < n; c += 64) Minv[(size_t)r * ldm + c] = TO(row[c] * sc);
+    const LDS double* row = Aug + perm[r] * ld + n + c0;
+    const double sc = dg[r] * scale;
+    for (int c = lane; c < m; c += 64) Out[(size_t)r * ldo + c] = TO(row[c] * sc);
   }
   __syncthreads();
+}
+
+// Inverse of M held in the left half of Aug = [M | I] (n x 2n): Minv (ldm).
+template <typename TO>
+__device__ inline bool wg_gj_inverse(int n, LDS double* Aug, bool pivot, LDS int* perm, LDS int* used,
+                                     LDS double* dg, TO* Minv, int ldm) {
+  if (!wg_gj_eliminate(n, 2 * n, Aug, pivot, perm, used, dg)) return false;
+  wg_gj_extract<TO>(n, 2 * n, Aug, perm, dg, 0, n, 1.0, Minv, ldm);
   return true;
 }
 

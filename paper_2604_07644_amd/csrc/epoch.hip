@@ -302,12 +302,25 @@ __global__ void __launch_bounds__(kWG) k_fixup(DevProblem<T> pb, DevEpochWork<T>
     wg_gemm<T>(nu, nu, nx, T(1), B, nu, true, PB, nu, false, T(1), Hs, nu, gsm);
     wg_gemm<T>(nu, nx, nx, T(1), B, nu, true, PA, nx, false, T(1), G, nx, gsm);
     wg_symmetrize(nu, Hs, nu);
-    // FP64 inverse of the symmetric positive definite H: Gamma = H^{-1}, K = -Gamma G
+    // FP64 elimination of [H | G | I] for the symmetric positive definite H:
+    // K = -H^{-1} G and Gamma = H^{-1}.  K is read from the elimination, not
+    // formed from a rounded Gamma (that would carry cond(H) times Gamma's
+    // rounding into K and from there into P).
     T* K = F + (size_t)nx * nxu;         // K block: rows nx.., columns 0..nx-1
     T* Gam = fc.Gam + (size_t)i * nu * nu;
-    fill_aug(nu, L.Aug, Hs);
-    if (!wg_gj_inverse<T>(nu, L.Aug, false, L.perm, L.used, L.dg, Gam, nu)) { flag_fail(ew.status); return; }
-    wg_gemm<T>(nu, nx, nu, T(-1), Gam, nu, false, G, nx, false, T(0), K, nxu, gsm);
+    const int lda = 2 * nu + nx;
+    for (int r = wave(); r < nu; r += 4)
+      for (int cc = lane(); cc < lda; cc += 64) {
+        double v;
+        if (cc < nu) v = double(Hs[(size_t)r * nu + cc]);
+        else if (cc < nu + nx) v = double(G[(size_t)r * nx + (cc - nu)]);
+        else v = (cc - nu - nx == r) ? 1.0 : 0.0;
+        L.Aug[r * lda + cc] = v;
+      }
+    __syncthreads();
+    if (!wg_gj_eliminate(nu, lda, L.Aug, false, L.perm, L.used, L.dg)) { flag_fail(ew.status); return; }
+    wg_gj_extract<T>(nu, lda, L.Aug, L.perm, L.dg, 0, nx, -1.0, K, nxu);
+    wg_gj_extract<T>(nu, lda, L.Aug, L.perm, L.dg, nx, nu, 1.0, Gam, nu);
     // Abar = A + B K  (block rows 0..nx-1, columns 0..nx-1 of F)
     wg_copy(nx, nx, F, nxu, A, nx);
     __syncthreads();

@@ -48,8 +48,8 @@ __host__ __device__ inline SlsLayout sls_layout(int nx, int nu, int nc, int nf) 
   L.M = o; o += 0;
   L.T = o; o += (size_t)(rows + 3) & ~(size_t)3;         // tau column / row norms
   o = (o + 3) & ~(size_t)3;
-  L.aug = o * 4;                                         // bytes: FP64 [Z_uu | I]
-  L.bytes = L.aug + sizeof(double) * ((size_t)nu * 2 * nu + 2 * nu) + 2 * sizeof(int) * nu + 64;
+  L.aug = o * 4;                                         // bytes: FP64 [Z_uu | Z_ux]
+  L.bytes = L.aug + sizeof(double) * ((size_t)nu * (nu + nx) + 2 * nu) + 2 * sizeof(int) * nu + 64;
   return L;
 }
 
@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(kWG) k_sls(SlsArgs a) {
   LDS float* Y = F + lay.Y;
   LDS float* Tv = F + lay.T;
   LDS double* aug = (LDS double*)(base + lay.aug);
-  LDS double* dg = aug + nu * 2 * nu;
+  LDS double* dg = aug + nu * (nu + nx);
   LDS int* perm = (LDS int*)(dg + 2 * nu);
   LDS int* used = perm + nu;
   __shared__ unsigned s_item;
@@ -132,21 +132,28 @@ __global__ void __launch_bounds__(kWG) k_sls(SlsArgs a) {
         for (int c = lane(); c < nxu; c += 64) W[r * lay.ldW + c] = Tv[r] * G[r * lay.ldG + c];
       __syncthreads();
       wg_mm_f32(nxu, nxu, nc, 1.f, G, lay.ldG, true, W, lay.ldW, false, 1.f, Z, lay.ldZ);
-      // Gamma = Z_uu^{-1} in FP64 (symmetric positive definite); K = -Gamma Z_ux
+      // K = -Z_uu^{-1} Z_ux by FP64 elimination of [Z_uu | Z_ux] (Z_uu symmetric
+      // positive definite).  Solving for K directly keeps P = Z_xx + Z_ux^T K
+      // accurate when the tau-weighted terms are large: a K formed from a
+      // rounded inverse carries cond(Z_uu) times its rounding into P.
+      const int lda = nu + nx;
       for (int r = wave(); r < nu; r += 4)
-        for (int c = lane(); c < 2 * nu; c += 64) {
-          const int zr = nx + r, zc = nx + (c < nu ? c : 0);
-          const double hv = 0.5 * ((double)Z[zr * lay.ldZ + zc] + (double)Z[zc * lay.ldZ + zr]);
-          aug[r * 2 * nu + c] = c < nu ? hv : (c - nu == r ? 1.0 : 0.0);
+        for (int c = lane(); c < lda; c += 64) {
+          double v;
+          if (c < nu) {
+            v = 0.5 * ((double)Z[(nx + r) * lay.ldZ + nx + c] + (double)Z[(nx + c) * lay.ldZ + nx + r]);
+          } else {
+            v = (double)Z[(nx + r) * lay.ldZ + (c - nu)];
+          }
+          aug[r * lda + c] = v;
         }
       __syncthreads();
-      LDS float* Gam = W;  // nu x nu, ld nu
-      if (!wg_gj_inverse<float>(nu, aug, false, perm, used, dg, (float*)Gam, nu)) {
+      if (!wg_gj_eliminate(nu, lda, aug, false, perm, used, dg)) {
         if (tid() == 0) atomicMax(a.status, 1);
         break;
       }
+      wg_gj_extract<float>(nu, lda, aug, perm, dg, 0, nx, -1.0, (float*)Y, lay.ldY);
       // K (in Y) and its copy in this workgroup's gain store for the forward pass
-      wg_mm_f32(nu, nx, nu, -1.f, Gam, nu, false, Z + nx * lay.ldZ, lay.ldZ, false, 0.f, Y, lay.ldY);
       float* Kk = Kst + (size_t)k * nu * nx;
       for (int r = wave(); r < nu; r += 4)
         for (int c = lane(); c < nx; c += 64) Kk[(size_t)r * nx + c] = Y[r * lay.ldY + c];

@@ -22,6 +22,7 @@ HOST, DEVICE = 0, 1
 MIXED, FP64 = 0, 1
 
 _dp = ct.POINTER(ct.c_double)
+_fp = ct.POINTER(ct.c_float)
 
 
 class QPDesc(ct.Structure):
@@ -41,7 +42,7 @@ class Result(ct.Structure):
     _fields_ = [("status", ct.c_int32), ("iterations", ct.c_int32), ("rho_updates", ct.c_int32),
                 ("factorizations", ct.c_int32), ("r_p", ct.c_double), ("r_d", ct.c_double),
                 ("rho", ct.c_double), ("ms_total", ct.c_double), ("ms_factor", ct.c_double),
-                ("ms_iterate", ct.c_double)]
+                ("ms_iterate", ct.c_double), ("cold_restart", ct.c_int32), ("reserved", ct.c_int32)]
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -56,6 +57,15 @@ class GslsError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libgsls.so not built at {LIB_PATH}; run paper_2604_07644_amd/build.py")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64 (soname
+    # libamdhip64.so.7, loaded through an unversioned dependency).  Loading
+    # torch first makes the library's libamdhip64.so.7 dependency resolve to
+    # that same runtime, so streams and device pointers from torch are valid
+    # here; loading the system runtime first would give the process two.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ct.CDLL(LIB_PATH)
     P = ct.c_void_p
     sig = {
@@ -78,6 +88,20 @@ def _load():
                                            ct.POINTER(Result), _dp]),
         "gsls_batch_get": (ct.c_int, [P, ct.c_int32, _dp, _dp, _dp, _dp]),
         "gsls_batch_free": (None, [P]),
+        "gsls_ws_nparams": (ct.c_int64, []),
+        "gsls_ws_create": (ct.c_int, [_fp, _fp, P, ct.POINTER(P)]),
+        "gsls_ws_get_params": (ct.c_int, [P, _fp]),
+        "gsls_ws_save": (ct.c_int, [P, ct.c_char_p]),
+        "gsls_ws_load": (ct.c_int, [ct.c_char_p, P, ct.POINTER(P)]),
+        "gsls_ws_forward": (ct.c_int, [P, P, ct.c_int32, P]),
+        "gsls_ws_loss_grad": (ct.c_int, [P, P, P, P, P, ct.c_int32, _fp, _fp]),
+        "gsls_ws_train_step": (ct.c_int, [P, P, P, P, P, ct.c_int32, ct.c_float, _fp]),
+        "gsls_ws_batch_rows": (ct.c_int32, [P]),
+        "gsls_ws_features": (ct.c_int, [P, P, ct.POINTER(_dp), P]),
+        "gsls_ws_targets": (ct.c_int, [P, P, P]),
+        "gsls_qp_solve_batch_ws": (ct.c_int, [P, P, ct.POINTER(_dp), ct.c_double, ct.c_int32, ct.POINTER(Result),
+                                              _dp, _dp]),
+        "gsls_ws_free": (None, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -147,7 +171,8 @@ class QP:
         self.result = None
 
     def close(self):
-        if getattr(self, "h", None):
+        # at interpreter exit the module global may already be gone
+        if getattr(self, "h", None) and lib is not None:
             lib.gsls_qp_free(self.h)
             self.h = None
 
@@ -247,7 +272,8 @@ class Batch:
         self.h = h
 
     def close(self):
-        if getattr(self, "h", None):
+        # at interpreter exit the module global may already be gone
+        if getattr(self, "h", None) and lib is not None:
             lib.gsls_batch_free(self.h)
             self.h = None
 
@@ -282,3 +308,127 @@ class Batch:
         if rc != OK:
             raise GslsError(rc, "gsls_batch_get")
         return dict(X=X, U=U, z=z, lam=lam)
+
+    def _x0_array(self, x0s):
+        n = len(self.probs)
+        x0s = [_f64(p.x0) for p in self.probs] if x0s is None else [_f64(x) for x in x0s]
+        return x0s, (_dp * n)(*[_ptr(x) for x in x0s])
+
+    def rows(self):
+        """Number of warm-start feature rows (sum of N + 1)."""
+        return int(lib.gsls_ws_batch_rows(self.h))
+
+    def solve_ws(self, ws, x0s=None, tol=1e-5, warm_budget=0):
+        """Learned warm start + solve (gsls_qp_solve_batch_ws).  Returns
+        (results, ms_total, ms_predict)."""
+        n = len(self.probs)
+        keep, xp = self._x0_array(x0s)
+        res = (Result * n)()
+        ms = np.zeros(1); msp = np.zeros(1)
+        rc = lib.gsls_qp_solve_batch_ws(self.h, ws.h, xp, float(tol), int(warm_budget), res, _ptr(ms), _ptr(msp))
+        if rc != OK:
+            raise GslsError(rc, "gsls_qp_solve_batch_ws")
+        self.results = [r.asdict() for r in res]
+        return self.results, float(ms[0]), float(msp[0])
+
+
+def _dev(t):
+    return ct.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class WarmStart:
+    """Learned warm-start model (gsls_ws_*).  Device arrays are torch tensors:
+    features torch.bfloat16 [rows, 160], targets / mask / outputs float32
+    [rows, 192], row indices int32."""
+
+    D_IN, D_OUT = 160, 192
+
+    def __init__(self, params=None, sketch=None, stream=None, path=None):
+        h = ct.c_void_p()
+        st = ct.c_void_p(stream) if stream else None
+        if path is not None:
+            rc = lib.gsls_ws_load(str(path).encode(), st, ct.byref(h))
+            where = "gsls_ws_load"
+        else:
+            p = np.ascontiguousarray(params, dtype=np.float32)
+            sk = np.ascontiguousarray(sketch, dtype=np.float32)
+            if p.size != self.nparams() or sk.size != 64 * 94:
+                raise GslsError(ERR_INVALID_ARG, "WarmStart: parameter or sketch size")
+            rc = lib.gsls_ws_create(p.ctypes.data_as(_fp), sk.ctypes.data_as(_fp), st, ct.byref(h))
+            where = "gsls_ws_create"
+        if rc != OK:
+            raise GslsError(rc, where)
+        self.h = h
+
+    @staticmethod
+    def nparams():
+        return int(lib.gsls_ws_nparams())
+
+    def close(self):
+        # at interpreter exit the module global may already be gone
+        if getattr(self, "h", None) and lib is not None:
+            lib.gsls_ws_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def params(self):
+        p = np.zeros(self.nparams(), dtype=np.float32)
+        rc = lib.gsls_ws_get_params(self.h, p.ctypes.data_as(_fp))
+        if rc != OK:
+            raise GslsError(rc, "gsls_ws_get_params")
+        return p
+
+    def save(self, path):
+        rc = lib.gsls_ws_save(self.h, str(path).encode())
+        if rc != OK:
+            raise GslsError(rc, "gsls_ws_save")
+
+    def forward(self, X):
+        import torch
+        Y = torch.empty((X.shape[0], self.D_OUT), dtype=torch.float32, device=X.device)
+        rc = lib.gsls_ws_forward(self.h, _dev(X), int(X.shape[0]), _dev(Y))
+        if rc != OK:
+            raise GslsError(rc, "gsls_ws_forward")
+        torch.cuda.synchronize()
+        return Y
+
+    def loss_grad(self, X, T, M, idx=None, rows=None):
+        rows = int(idx.shape[0] if idx is not None else X.shape[0]) if rows is None else int(rows)
+        g = np.zeros(self.nparams(), dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        rc = lib.gsls_ws_loss_grad(self.h, _dev(X), _dev(T), _dev(M), _dev(idx), rows, g.ctypes.data_as(_fp),
+                                   loss.ctypes.data_as(_fp))
+        if rc != OK:
+            raise GslsError(rc, "gsls_ws_loss_grad")
+        return float(loss[0]), g
+
+    def train_step(self, X, T, M, idx=None, rows=None, lr=1e-3, want_loss=False):
+        rows = int(idx.shape[0] if idx is not None else X.shape[0]) if rows is None else int(rows)
+        loss = np.zeros(1, dtype=np.float32)
+        rc = lib.gsls_ws_train_step(self.h, _dev(X), _dev(T), _dev(M), _dev(idx), rows, float(lr),
+                                    loss.ctypes.data_as(_fp) if want_loss else None)
+        if rc != OK:
+            raise GslsError(rc, "gsls_ws_train_step")
+        return float(loss[0]) if want_loss else None
+
+    def features(self, batch, x0s=None):
+        import torch
+        X = torch.empty((batch.rows(), self.D_IN), dtype=torch.bfloat16, device="cuda")
+        keep, xp = batch._x0_array(x0s)
+        rc = lib.gsls_ws_features(self.h, batch.h, xp, _dev(X))
+        if rc != OK:
+            raise GslsError(rc, "gsls_ws_features")
+        return X
+
+    @staticmethod
+    def targets(batch):
+        import torch
+        n = batch.rows()
+        T = torch.empty((n, WarmStart.D_OUT), dtype=torch.float32, device="cuda")
+        M = torch.empty_like(T)
+        rc = lib.gsls_ws_targets(batch.h, _dev(T), _dev(M))
+        if rc != OK:
+            raise GslsError(rc, "gsls_ws_targets")
+        return T, M

@@ -75,3 +75,14 @@ def test_null_handle_calls_fail_cleanly():
     assert gsls.lib.gsls_qp_solve(None, x0.ctypes.data_as(gsls._dp), 1.0, 1e-5, ct.byref(r)) == gsls.ERR_INVALID_ARG
     assert gsls.lib.gsls_qp_get(None, None, None, None, None) == gsls.ERR_INVALID_ARG
     gsls.lib.gsls_qp_free(None)
+
+
+def test_one_hip_runtime_per_process():
+    """The binding loads PyTorch's HIP runtime before the library, so a process
+    that uses both holds exactly one libamdhip64 (two runtimes cannot share
+    streams or device pointers)."""
+    import paper_2604_07644_amd.gsls  # noqa: F401
+    import torch  # noqa: F401
+    maps = open("/proc/self/maps").read().splitlines()
+    libs = {ln.split()[-1] for ln in maps if "libamdhip64" in ln}
+    assert len(libs) == 1, libs

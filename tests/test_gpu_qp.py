@@ -15,7 +15,7 @@ from paper_2604_07644_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-gsls = pytest.importorskip("paper_2604_07644_amd.gsls")
+from paper_2604_07644_amd import gsls  # noqa: E402  (fails loudly without libgsls.so)
 
 
 def _err(a, b):

@@ -12,7 +12,7 @@ from paper_2604_07644_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-gsls = pytest.importorskip("paper_2604_07644_amd.gsls")
+from paper_2604_07644_amd import gsls  # noqa: E402  (fails loudly without libgsls.so)
 
 
 def _rel(a, b):
@@ -83,3 +83,34 @@ def test_sls_tau_matches_oracle():
     q.close()
     to = oracle.sls_tau(p, lam, o["Phi_x"], o["Phi_u"], eps=1e-8)
     assert _rel(t, to) < 1e-4
+
+
+def test_sls_with_appendix_b_tau_pipeline():
+    """The SLS workload's pipeline on one quadruped-shaped instance (N=64):
+    nominal ADMM multipliers, tau of App. B from the tau = 0 responses, then
+    the tau-weighted SLS.  Each GPU stage is checked against the oracle fed
+    the same inputs (tau reaches ~5e5 here, where the penalty of rows with no
+    disturbance response is |lambda| / sqrt(eps))."""
+    probs, E, wb = W.sls_batch(2)
+    p = probs[0]
+    Qb, Rb, QbN = np.eye(p.nx), np.eye(p.nu), np.eye(p.nx)
+    zero = np.zeros(p.N * p.N * p.nc + p.N * p.nf)
+    base = oracle.sls_solve(p, E, zero, Qb, Rb, QbN, rownorm=1, wbound=wb)
+    nom = oracle.qp_solve(p, rho=1.0, tol=1e-5)
+    tau_o = oracle.sls_tau(p, nom["lam"], base["Phi_x"], base["Phi_u"])
+    q = gsls.QP(p)
+    # tau on the GPU from the same multipliers and responses
+    tau_g = q.sls_tau(nom["lam"], base["Phi_x"], base["Phi_u"])
+    np.testing.assert_allclose(tau_g, tau_o, rtol=1e-3, atol=1e-6)
+    # SLS on the GPU with the oracle's tau
+    g = q.sls_solve(E, tau_o, Qb, Rb, QbN, rownorm=1, wbound=wb, want_phi=False)
+    o = oracle.sls_solve(p, E, tau_o, Qb, Rb, QbN, rownorm=1, wbound=wb, want_phi=False)
+    assert _rel(g["h"], o["h"]) < 1e-3, _rel(g["h"], o["h"])
+    # the batched entry point with two instances' tau
+    nom1 = oracle.qp_solve(probs[1], rho=1.0, tol=1e-5)
+    tau1 = oracle.sls_tau(probs[1], nom1["lam"], base["Phi_x"], base["Phi_u"])
+    r = q.sls_solve_batch(E, [tau_o, tau1], Qb, Rb, QbN, rownorm=1, wbound=wb)
+    assert _rel(r["h"][0], o["h"]) < 1e-3
+    o1 = oracle.sls_solve(probs[1], E, tau1, Qb, Rb, QbN, rownorm=1, wbound=wb, want_phi=False)
+    assert _rel(r["h"][1], o1["h"]) < 1e-3
+    q.close()

@@ -107,8 +107,9 @@ typedef struct gsls_result {
   double r_d;            /* rho |G^T (z+ - z)|_inf at the last iteration          */
   double rho;            /* final rho                                             */
   double ms_total;       /* device time of the whole solve (HIP events)           */
-  double ms_factor;      /* device time spent in factor epochs                    */
-  double ms_iterate;     /* device time spent in the ADMM iteration kernel        */
+  double ms_factor;      /* device time spent in factor epochs (batched solves:
+                            time of the instance's own workgroup)              */
+  double ms_iterate;     /* device time spent in the ADMM iterations (same)       */
   int32_t cold_restart;  /* batched learned warm start: 1 if the instance did not
                             converge within the warm budget and was re-solved
                             from a cold start (its iterations include both)    */
@@ -229,6 +230,12 @@ int gsls_qp_solve_batch(gsls_batch* b, const double* const* x0, const double* rh
 int gsls_batch_get(gsls_batch* b, int32_t index, double* X, double* U, double* z, double* lambda);
 
 void gsls_batch_free(gsls_batch* b);
+
+/* Diagnostics: enable != 0 turns on per-phase device-clock counters of the
+ * batched iterations (summed over instances; they add one barrier per
+ * phase), 0 turns them off.  cycles16 (nullable) receives the counters
+ * accumulated since the previous call, which are then cleared. */
+int gsls_batch_debug_phase_cycles(gsls_batch* b, int32_t enable, double* cycles16);
 
 /* ------------------------------------------------------------------------
  * Learned warm start of the batched solver (an extension of the ADMM start of

@@ -34,24 +34,52 @@ constexpr int kBatchMaxNxu = 96;
 
 __host__ __device__ inline int bodd(int x) { return x | 1; }
 
+// Per-stage packet of the cached iteration operators, one contiguous block per
+// stage in the float pool: F = [[Abar, B], [K, I]] (odd leading dimension, so
+// that both F x and F^T x read LDS without bank conflicts), Gamma, ev =
+// Abar^T P b, fv = B^T P b, and the stage's constant data q, r, b.  The
+// iterations stream these packets through LDS.
+struct PkLayout {
+  int ldF, F, Gam, ev, fv, q, r, b, stride;
+};
+__host__ __device__ inline PkLayout pk_layout(int nx, int nu) {
+  PkLayout L;
+  const int nxu = nx + nu;
+  L.ldF = bodd(nxu);
+  int o = 0;
+  L.F = o; o += nxu * L.ldF;
+  L.Gam = o; o += nu * nu;
+  L.ev = o; o += nx;
+  L.fv = o; o += nu;
+  L.q = o; o += nx;
+  L.r = o; o += nu;
+  L.b = o; o += nx;
+  L.stride = (o + 3) & ~3;
+  return L;
+}
+constexpr int kPkVec = 11;      // 16-byte packet slices per thread (stride <= 44 * kWG)
+
 struct BLayout {
   int ldP, ldW, ldZ, ldAB, ldG, ldY;
-  size_t P, W, Z, AB, G, Y, vec, bytes;
-  size_t aug, dg, red, perm;   // FP64 / int scratch inside the W region (byte offsets)
+  size_t P, W, Z, AB, G, Y, pk0, pk1, vec, bytes;
+  size_t aug, dg, perm, red;   // byte offsets: FP64 / int scratch of the epoch (in the
+                               // W region) and the reduction buffer of the iterations
+  size_t prof;                 // byte offset: 16 phase counters (profiling only)
 };
 // nc: rows held in the G buffer (0 on the box fast path, else max(nc, nf)).
 // Float regions start on 16-byte boundaries.  The Gauss-Jordan block
-// ([Z_uu | I] in FP64, pivots) and the reduction buffer of the iterations
-// live in the W region, which is dead while they are in use.
+// ([Z_uu | Z_ux | I] in FP64, pivots) lives in the W region, which is dead
+// while it is in use.  The two packet buffers of the iterations alias the
+// epoch's regions (the epoch and the iterations never overlap in time).
 __host__ __device__ inline BLayout batch_layout(int nx, int nu, int nc) {
   BLayout L;
   const int nxu = nx + nu;
   L.ldP = bodd(nx); L.ldW = bodd(nxu); L.ldZ = bodd(nxu); L.ldAB = bodd(nxu); L.ldG = bodd(nxu);
   L.ldY = bodd(nx);
   auto r4 = [](size_t v) { return (v + 3) & ~(size_t)3; };
-  const size_t aug_d = (size_t)nu * (2 * nu + nx), dg_d = 32, red_d = kWG, perm_d = 32;
+  const size_t aug_d = (size_t)nu * (2 * nu + nx), dg_d = 32, perm_d = 32;
   const size_t wfl = r4((size_t)(nx > nc ? nx : nc) * L.ldW);
-  const size_t afl = 2 * (aug_d + dg_d + red_d + perm_d);
+  const size_t afl = 2 * (aug_d + dg_d + perm_d);
   size_t o = 0;
   L.P = o; o += r4((size_t)nx * L.ldP);
   L.W = o; o += wfl > afl ? wfl : afl;
@@ -59,12 +87,20 @@ __host__ __device__ inline BLayout batch_layout(int nx, int nu, int nc) {
   L.AB = o; o += r4((size_t)nx * L.ldAB);
   L.G = o; o += r4((size_t)nc * L.ldG);
   L.Y = o; o += r4((size_t)nu * L.ldY);
+  const size_t pkf = (size_t)kPkVec * 4 * kWG;   // a packet buffer holds a full prefetch
+  L.pk0 = 0;
+  L.pk1 = pkf;
+  if (o < 2 * pkf) o = 2 * pkf;
   L.vec = o; o += 8 * kBV + 512;
+  o = r4(o);
+  const size_t redf = o; o += 2 * (kWG + 8);
+  const size_t proff = o; o += 2 * 16;
   L.bytes = o * 4;
   L.aug = L.W * 4;
   L.dg = L.aug + aug_d * 8;
-  L.red = L.dg + dg_d * 8;
-  L.perm = L.red + red_d * 8;
+  L.perm = L.dg + dg_d * 8;
+  L.red = redf * 4;
+  L.prof = proff * 4;
   return L;
 }
 
@@ -73,22 +109,27 @@ constexpr size_t kBatchLdsMax = 160 * 1024 - 512;
 
 __device__ inline double wg_max_d(double v, LDS double* s) {
   s[tid()] = v;
-  __syncthreads();
+  lds_barrier();
   for (int st = kWG / 2; st > 0; st >>= 1) {
     if (tid() < st) {
       double a = s[tid()], b = s[tid() + st];
       s[tid()] = (b > a || b != b) ? b : a;
     }
-    __syncthreads();
+    lds_barrier();
   }
   double r = s[0];
-  __syncthreads();
+  lds_barrier();
   return r;
 }
 
 // Factor epoch of one instance for penalty rho.  Returns false if a Z_uu block
 // is not positive definite.
-__device__ bool batch_epoch(const BInst& I, const BatchArgs& a, double rho, LDS char* base) {
+__device__ __attribute__((noinline)) bool batch_epoch(const BInst* __restrict__ Ip, const BatchArgs* __restrict__ ag,
+                                                     double rho, LDS char* base) {
+  Ip = uniform_ptr(Ip);
+  ag = uniform_ptr(ag);
+  const BInst& I = *Ip;
+  const BatchArgs& a = *ag;
   const int N = I.N, nx = I.nx, nu = I.nu, nc = I.nc, nf = I.nf, nxu = nx + nu;
   const BLayout lay = batch_layout(nx, nu, I.box ? 0 : (nc > nf ? nc : nf));
   LDS float* F0 = (LDS float*)base;
@@ -173,23 +214,25 @@ __device__ bool batch_epoch(const BInst& I, const BatchArgs& a, double rho, LDS 
         aug[r * lda + c] = v;
       }
     __syncthreads();
-    float* Gam = fp + I.oGam + (size_t)k * nu * nu;
+    const PkLayout pk = pk_layout(nx, nu);
+    float* pkt = fp + I.oPk + (size_t)k * pk.stride;
+    float* Gam = pkt + pk.Gam;
     if (!wg_gj_eliminate(nu, lda, aug, false, perm, used, dg)) return false;
     wg_gj_extract<float>(nu, lda, aug, perm, dg, 0, nx, -1.0, (float*)Y, lay.ldY);
     wg_gj_extract<float>(nu, lda, aug, perm, dg, nx, nu, 1.0, Gam, nu);
     // F = [[A + B K, B], [K, I]]
-    float* Fk = fp + I.oF + (size_t)k * nxu * nxu;
+    float* Fk = pkt + pk.F;
     wg_mm_f32(nx, nx, nu, 1.f, AB + nx, lay.ldAB, false, Y, lay.ldY, false, 0.f, W, lay.ldW);  // B K
     for (int r = wave(); r < nxu; r += 4)
       for (int c = lane(); c < nxu; c += 64) {
         float v;
         if (r < nx) v = c < nx ? AB[r * lay.ldAB + c] + W[r * lay.ldW + c] : AB[r * lay.ldAB + c];
         else v = c < nx ? Y[(r - nx) * lay.ldY + c] : (c - nx == r - nx ? 1.f : 0.f);
-        Fk[(size_t)r * nxu + c] = v;
+        Fk[(size_t)r * pk.ldF + c] = v;
       }
     // ev = Abar^T P b, fv = B^T P b
-    float* ev = fp + I.oev + (size_t)k * nx;
-    float* fv = fp + I.ofv + (size_t)k * nu;
+    float* ev = pkt + pk.ev;
+    float* fv = pkt + pk.fv;
     for (int c = tid(); c < nxu; c += kWG) {
       float s = 0.f;
       for (int r = 0; r < nx; ++r) {
@@ -214,215 +257,471 @@ __device__ bool batch_epoch(const BInst& I, const BatchArgs& a, double rho, LDS 
   return true;
 }
 
+// Light GEMVs for operands already in LDS (or read rarely): the reduction is
+// split over the four waves (row w + 4k), each thread keeping only a running
+// sum, so they add little register pressure next to the packet prefetch.
+// y = M^T x for M m x n (m any, n <= 128), y = M x for M m x n (m <= 128).
+template <typename PM, typename PX, typename PY>
+__device__ __forceinline__ void lite_gemv_t(int m, int n, PM M, int ld, PX x, PY y, LDS float* part) {
+  // keep the per-call index arithmetic inside the caller's loops (hoisting it
+  // out of a stage loop would hold many registers for the whole loop)
+  asm volatile("" : "+v"(ld));
+  const int lane = tid() & 63, w = tid() >> 6;
+  for (int jb = 0; jb * 64 < n; ++jb) {
+    const int j = jb * 64 + lane;
+    const int jc = min(j, n - 1);
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int i = w;
+    for (; i + 12 < m; i += 16) {
+      s0 += float(M[i * ld + jc]) * float(x[i]);
+      s1 += float(M[(i + 4) * ld + jc]) * float(x[i + 4]);
+      s2 += float(M[(i + 8) * ld + jc]) * float(x[i + 8]);
+      s3 += float(M[(i + 12) * ld + jc]) * float(x[i + 12]);
+    }
+    for (; i < m; i += 4) s0 += float(M[i * ld + jc]) * float(x[i]);
+    part[w * 128 + j] = (s0 + s1) + (s2 + s3);
+  }
+  lds_barrier();
+  for (int j = tid(); j < n; j += kWG) y[j] = part[j] + part[128 + j] + part[256 + j] + part[384 + j];
+  lds_barrier();
+}
+template <typename PM, typename PX, typename PY>
+__device__ __forceinline__ void lite_gemv_n(int m, int n, PM M, int ld, PX x, PY y, LDS float* part, bool acc) {
+  asm volatile("" : "+v"(ld));
+  const int lane = tid() & 63, w = tid() >> 6;
+  for (int ib = 0; ib * 64 < m; ++ib) {
+    const int i = ib * 64 + lane;
+    const int ic = min(i, m - 1);
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int k = w;
+    for (; k + 12 < n; k += 16) {
+      s0 += float(M[ic * ld + k]) * float(x[k]);
+      s1 += float(M[ic * ld + k + 4]) * float(x[k + 4]);
+      s2 += float(M[ic * ld + k + 8]) * float(x[k + 8]);
+      s3 += float(M[ic * ld + k + 12]) * float(x[k + 12]);
+    }
+    for (; k < n; k += 4) s0 += float(M[ic * ld + k]) * float(x[k]);
+    part[w * 128 + i] = (s0 + s1) + (s2 + s3);
+  }
+  lds_barrier();
+  for (int i = tid(); i < m; i += kWG) {
+    const float v = part[i] + part[128 + i] + part[256 + i] + part[384 + i];
+    y[i] = acc ? float(y[i]) + v : v;
+  }
+  lds_barrier();
+}
+
+// Stage packets move global -> LDS by DMA (buffer loads with the LDS
+// destination): no registers hold the data, so the copy of the next stage's
+// packet runs while the current stage is processed.  Each 16-byte slice of
+// wave w lands at M0 + 16 * lane with M0 = dst + slice * 1024 floats + w * 256
+// floats, i.e. at the same offset as in global memory; reads past n floats
+// return 0.  Completion: pk_dma_wait() (all of the wave's vector memory
+// operations), then a barrier.
+__device__ __forceinline__ void pk_dma_issue(const float* src, int n, LDS float* dst) {
+  src = uniform_ptr(src);
+  n = __builtin_amdgcn_readfirstlane(n);
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)src, (short)0, n * 4, 0x00020000);
+  const int w = (int)tid() >> 6;
+  const int vo = (int)tid() * 16;
+#pragma unroll
+  for (int q = 0; q < kPkVec; ++q)
+    if (q * kWG * 4 < n)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (LDS void*)(dst + q * kWG * 4 + w * 256), 16, vo, q * kWG * 16, 0,
+                                               0);
+}
+__device__ __forceinline__ void pk_dma_wait() { __builtin_amdgcn_s_waitcnt(0); }
+
+// Work vectors of the iterations in LDS.
+struct IterVecs {
+  LDS float *g, *g2, *xz, *tv, *tu, *wv, *wv2, *part;
+  LDS double* red;
+  LDS unsigned long long* pc;
+  LDS float* buf[2];
+};
+__device__ __forceinline__ IterVecs iter_vecs(const BLayout& lay, LDS char* base) {
+  IterVecs v;
+  LDS float* F0 = (LDS float*)base;
+  v.buf[0] = F0 + lay.pk0;
+  v.buf[1] = F0 + lay.pk1;
+  v.g = F0 + lay.vec;
+  v.g2 = v.g + kBV;
+  v.xz = v.g2 + kBV;
+  v.tv = v.xz + kBV;
+  v.tu = v.tv + kBV;
+  v.wv = v.tu + kBV;
+  v.wv2 = v.wv + kBV;
+  v.part = v.wv2 + 2 * kBV;
+  v.red = (LDS double*)(base + lay.red);
+  v.pc = (LDS unsigned long long*)(base + lay.prof);
+  return v;
+}
+
+// Optional phase profile: device clock between marks, summed per phase (LDS
+// counters, thread 0).
+struct PhaseMark {
+  LDS unsigned long long* pc;
+  bool on;
+  unsigned long long last = 0;
+  __device__ __forceinline__ void operator()(int ph) {
+    if (on) {
+      lds_barrier();
+      const unsigned long long tn = __builtin_amdgcn_s_memtime();
+      if (tid() == 0 && last) pc[ph] += tn - last;
+      last = tn;
+    }
+  }
+};
+
+// Backward pass of one cached iteration (Sec. IV-A): p_N = cst q_N + rho C_N^T dw_N,
+// then per stage k = N-1..0, from the stage packet in LDS,
+//   F^T [p; r_hat] = [Abar^T p + K^T r_hat; B^T p + r_hat]  (F = [[Abar, B], [K, I]]),
+//   p_k = Abar^T p + K^T r_hat + cst (q_k + ev_k) + rho C_k^T dw,
+//   k_k = -Gamma (B^T p + r_hat + cst fv_k),  r_hat = cst r_k + rho D_k^T dw,
+// with dw the increment of w = y - z (w itself on a full evaluation, cst = 1).
+// Writes k_k to the feed-forward store.  Thread r handles constraint row r of
+// every stage (so its global reads are its own writes: LDS-only barriers).
+template <bool BOX>
+__device__ __attribute__((noinline)) void batch_backward(const BInst* __restrict__ Ip,
+                                                         const BatchArgs* __restrict__ ag, float fr, bool full,
+                                                         LDS char* base) {
+  Ip = uniform_ptr(Ip);
+  ag = uniform_ptr(ag);
+  const BInst& I = *Ip;
+  const BatchArgs& a = *ag;
+  const int N = I.N, nx = I.nx, nu = I.nu, nc = I.nc, nf = I.nf, nxu = nx + nu;
+  const BLayout lay = batch_layout(nx, nu, BOX ? 0 : (nc > nf ? nc : nf));
+  const PkLayout pk = pk_layout(nx, nu);
+  const int pst = pk.stride;
+  const IterVecs V = iter_vecs(lay, base);
+  const float* fp = a.fp;
+  double* dp = a.dp;
+  const float* pkt = fp + I.oPk;
+  const GLB double* ys = (const GLB double*)(dp + I.oy);
+  const GLB double* zs = (const GLB double*)(dp + I.oz);
+  GLB double* wprev = (GLB double*)(dp + I.owp);
+  GLB float* kff = (GLB float*)(a.fp + I.okff);
+  const float cst = full ? 1.f : 0.f;
+  const int t = tid();
+  PhaseMark mark{V.pc, a.prof != nullptr};
+  for (int r = t; r < nf; r += kWG) {
+    const size_t gr = (size_t)N * nc + r;
+    const double w = ys[gr] - zs[gr];
+    V.wv[r] = (float)(full ? w : w - wprev[gr]);
+    wprev[gr] = w;
+  }
+  lds_barrier();
+  if (nf > 0 && !BOX) lite_gemv_t(nf, nx, (const float*)(fp + I.oCN), nx, V.wv, V.tv, V.part);
+  for (int j = t; j < nx; j += kWG) {
+    const float cw = nf > 0 ? (BOX ? V.wv[j] : V.tv[j]) : 0.f;
+    V.g[j] = cst * fp[I.oq + (size_t)N * nx + j] + fr * cw;
+  }
+  pk_dma_issue(pkt + (size_t)(N - 1) * pst, pst, V.buf[0]);
+  double ry = 0.0, rz = 0.0, rw = 0.0;
+  if (t < nc) {
+    const size_t gr = (size_t)(N - 1) * nc + t;
+    ry = ys[gr]; rz = zs[gr]; rw = wprev[gr];
+  }
+  pk_dma_wait();
+  lds_barrier();
+  int cb = 0;
+  for (int i = N - 1; i >= 0; --i) {
+    LDS float* P = V.buf[cb];
+    double ny = 0.0, nz = 0.0, nw = 0.0;
+    if (i > 0) {
+      pk_dma_issue(pkt + (size_t)(i - 1) * pst, pst, V.buf[cb ^ 1]);
+      if (t < nc) {
+        const size_t gr = (size_t)(i - 1) * nc + t;
+        ny = ys[gr]; nz = zs[gr]; nw = wprev[gr];
+      }
+    }
+    mark(0);
+    if (t < nc) {
+      const double w = ry - rz;
+      V.wv[t] = (float)(full ? w : w - rw);
+      wprev[(size_t)i * nc + t] = w;
+    }
+    lds_barrier();
+    mark(1);
+    if (!BOX) {
+      if (nc > 0) {
+        lite_gemv_t(nc, nxu, (const float*)(fp + I.oG + (size_t)i * nc * nxu), nxu, V.wv, V.tv, V.part);
+      } else {
+        for (int j = t; j < nxu; j += kWG) V.tv[j] = 0.f;
+        lds_barrier();
+      }
+    }
+    // xz = [p; r_hat],  wv2 = q_hat + ev (state part of c_k without K^T r_hat)
+    for (int j = t; j < nxu; j += kWG) {
+      const float gw = BOX ? V.wv[j] : V.tv[j];
+      if (j < nx) {
+        V.xz[j] = V.g[j];
+        V.wv2[j] = cst * (P[pk.q + j] + P[pk.ev + j]) + fr * gw;
+      } else {
+        V.xz[j] = cst * P[pk.r + (j - nx)] + fr * gw;
+      }
+    }
+    lds_barrier();
+    mark(2);
+    lite_gemv_t(nxu, nxu, (const LDS float*)(P + pk.F), pk.ldF, V.xz, V.g2, V.part);
+    mark(3);
+    for (int j = t; j < nxu; j += kWG) {
+      if (j < nx) V.g[j] = V.g2[j] + V.wv2[j];
+      else V.tu[j - nx] = V.g2[j] + cst * P[pk.fv + (j - nx)];
+    }
+    lds_barrier();
+    lite_gemv_t(nu, nu, (const LDS float*)(P + pk.Gam), nu, V.tu, V.g2, V.part);
+    for (int j = t; j < nu; j += kWG) kff[(size_t)i * nu + j] = -V.g2[j];
+    mark(4);
+    ry = ny; rz = nz; rw = nw;
+    pk_dma_wait();
+    lds_barrier();
+    mark(5);
+    cb ^= 1;
+  }
+}
+
+// |H xi| on the accumulated iterate (rho rule's dual scale): max over the
+// stages of |Q x + S^T u| and |S x + R u| (Q_N x_N at the terminal stage).
+// Returns the workgroup maximum.
+__device__ __attribute__((noinline)) double batch_hxi(const BInst* __restrict__ Ip,
+                                                      const BatchArgs* __restrict__ ag, LDS char* base) {
+  Ip = uniform_ptr(Ip);
+  ag = uniform_ptr(ag);
+  const BInst& I = *Ip;
+  const BatchArgs& a = *ag;
+  const int N = I.N, nx = I.nx, nu = I.nu, nc = I.nc, nf = I.nf;
+  const BLayout lay = batch_layout(nx, nu, I.box ? 0 : (nc > nf ? nc : nf));
+  const IterVecs V = iter_vecs(lay, base);
+  const float* fp = a.fp;
+  const GLB double* X = (const GLB double*)(a.dp + I.oX);
+  const GLB double* U = (const GLB double*)(a.dp + I.oU);
+  const int t = tid();
+  double hx = 0.0;
+  for (int i = 0; i <= N; ++i) {
+  const bool term = i == N;
+  for (int j = t; j < nx; j += kWG) V.tv[j] = (float)X[(size_t)i * nx + j];
+  if (!term)
+    for (int j = t; j < nu; j += kWG) V.tu[j] = (float)U[(size_t)i * nu + j];
+  lds_barrier();
+  lite_gemv_n(nx, nx, (const float*)(fp + I.oQ + (size_t)i * nx * nx), nx, V.tv, V.wv2, V.part, false);
+  if (!term) {
+    lite_gemv_t(nu, nx, (const float*)(fp + I.oS + (size_t)i * nu * nx), nx, V.tu, V.wv, V.part);
+    for (int j = t; j < nx; j += kWG) V.wv2[j] += V.wv[j];
+    lite_gemv_n(nu, nu, (const float*)(fp + I.oR + (size_t)i * nu * nu), nu, V.tu, V.g, V.part, false);
+    lite_gemv_n(nu, nx, (const float*)(fp + I.oS + (size_t)i * nu * nx), nx, V.tv, V.g, V.part, true);
+    for (int j = t; j < nu; j += kWG) hx = fmax(hx, fabs((double)V.g[j]));
+  }
+  for (int j = t; j < nx; j += kWG) hx = fmax(hx, fabs((double)V.wv2[j]));
+  lds_barrier();
+  }
+  return wg_max_d(hx, V.red);
+}
+
+// Forward pass of one cached iteration: x_0 = cst x0, per stage
+// F [x; k] = [Abar x + B k; K x + k] gives u_k and x_{k+1} (+ cst b_k), the
+// constraint values v = G [x; u] (box rows: v = [x; u]), then the projection
+// z+ = clip(v + y, l, u), the scaled dual y+ = y + v - z+, and the residual
+// terms.  x, u, v accumulate in FP64 (increments after the first evaluation).
+// Returns, reduced over the workgroup, r_p, r_d and (rho-rule iterations)
+// |v|, |z|, |H xi|, |G^T lambda| / rho in out[0..5] (LDS).
+template <bool BOX>
+__device__ __attribute__((noinline)) void batch_forward(const BInst* __restrict__ Ip,
+                                                        const BatchArgs* __restrict__ ag, double rho, bool full,
+                                                        bool sigma_it, LDS char* base) {
+  Ip = uniform_ptr(Ip);
+  ag = uniform_ptr(ag);
+  const BInst& I = *Ip;
+  const BatchArgs& a = *ag;
+  const int N = I.N, nx = I.nx, nu = I.nu, nc = I.nc, nf = I.nf, nxu = nx + nu;
+  const BLayout lay = batch_layout(nx, nu, BOX ? 0 : (nc > nf ? nc : nf));
+  const PkLayout pk = pk_layout(nx, nu);
+  const int pst = pk.stride;
+  const IterVecs V = iter_vecs(lay, base);
+  const float* fp = a.fp;
+  double* dp = a.dp;
+  const float* pkt = fp + I.oPk;
+  GLB double* ys = (GLB double*)(dp + I.oy);
+  GLB double* zs = (GLB double*)(dp + I.oz);
+  GLB double* vacc = (GLB double*)(dp + I.ov);
+  const GLB double* ls = (const GLB double*)(dp + I.ol);
+  const GLB double* us = (const GLB double*)(dp + I.ou);
+  GLB double* X = (GLB double*)(dp + I.oX);
+  GLB double* U = (GLB double*)(dp + I.oU);
+  const GLB float* kff = (const GLB float*)(fp + I.okff);
+  const GLB float* x0 = (const GLB float*)(fp + I.ox0);
+  const float cst = full ? 1.f : 0.f;
+  const int t = tid();
+  PhaseMark mark{V.pc, a.prof != nullptr};
+  double rp = 0.0, rd = 0.0, vmax = 0.0, zmax = 0.0, hx = 0.0, gl = 0.0;
+  for (int j = t; j < nx; j += kWG) V.xz[j] = cst * x0[j];
+  pk_dma_issue(pkt, pst, V.buf[0]);
+  double sv = 0.0, sy = 0.0, sz = 0.0, sl = 0.0, su = 0.0, sX = 0.0, sU = 0.0;
+  if (t < nc) { sv = vacc[t]; sy = ys[t]; sz = zs[t]; sl = ls[t]; su = us[t]; }
+  if (t < nx) sX = X[t];
+  if (t < nu) sU = U[t];
+  pk_dma_wait();
+  lds_barrier();
+  int cb = 0;
+  for (int i = 0; i <= N; ++i) {
+    const bool term = (i == N);
+    const int nr = term ? nf : nc;
+    LDS float* P = V.buf[cb];
+    double nv = 0.0, ny = 0.0, nz = 0.0, nl = 0.0, nu_ = 0.0, nX = 0.0, nU = 0.0;
+    if (i + 1 < N) pk_dma_issue(pkt + (size_t)(i + 1) * pst, pst, V.buf[cb ^ 1]);
+    if (i + 1 <= N) {
+      const int nr1 = (i + 1 == N) ? nf : nc;
+      if (t < nr1) {
+        const size_t gr = (size_t)(i + 1) * nc + t;
+        nv = vacc[gr]; ny = ys[gr]; nz = zs[gr]; nl = ls[gr]; nu_ = us[gr];
+      }
+      if (t < nx) nX = X[(size_t)(i + 1) * nx + t];
+      if (i + 1 < N && t < nu) nU = U[(size_t)(i + 1) * nu + t];
+    }
+    if (t < nx) X[(size_t)i * nx + t] = full ? (double)V.xz[t] : sX + (double)V.xz[t];
+    mark(6);
+    if (!term) {
+      for (int j = t; j < nu; j += kWG) V.xz[nx + j] = kff[(size_t)i * nu + j];
+      lds_barrier();
+      mark(7);
+      lite_gemv_n(nxu, nxu, (const LDS float*)(P + pk.F), pk.ldF, V.xz, V.g2, V.part, false);
+      mark(8);
+      if (t < nu) {
+        const float uu = V.g2[nx + t];
+        V.xz[nx + t] = uu;
+        U[(size_t)i * nu + t] = full ? (double)uu : sU + (double)uu;
+      }
+      lds_barrier();
+      if (BOX) {
+        for (int r = t; r < nc; r += kWG) V.wv[r] = V.xz[r];
+      } else if (nc > 0) {
+        lite_gemv_n(nc, nxu, (const float*)(fp + I.oG + (size_t)i * nc * nxu), nxu, V.xz, V.wv, V.part, false);
+      }
+    } else if (nr > 0) {
+      if (BOX) {
+        for (int r = t; r < nf; r += kWG) V.wv[r] = V.xz[r];
+      } else {
+        lite_gemv_n(nf, nx, (const float*)(fp + I.oCN), nx, V.xz, V.wv, V.part, false);
+      }
+    }
+    lds_barrier();
+    mark(9);
+    if (t < nr) {
+      const size_t gr = (size_t)i * nc + t;
+      const double v = full ? (double)V.wv[t] : sv + (double)V.wv[t];
+      vacc[gr] = v;
+      const double tt = v + sy;
+      const double zn = tt < sl ? sl : (tt > su ? su : tt);
+      const double yn = sy + v - zn;
+      zs[gr] = zn;
+      ys[gr] = yn;
+      const double e = fabs(v - zn);
+      rp = (e > rp || e != e) ? e : rp;
+      vmax = fmax(vmax, fabs(v));
+      zmax = fmax(zmax, fabs(zn));
+      V.wv[t] = (float)(zn - sz);
+      V.wv2[t] = (float)yn;
+    }
+    lds_barrier();
+    if (nr > 0) {
+      if (BOX) {
+        if (t < nr) {
+          const double q = rho * fabs((double)V.wv[t]);
+          rd = (q > rd || q != q) ? q : rd;
+          if (sigma_it) gl = fmax(gl, rho * fabs((double)V.wv2[t]));
+        }
+      } else {
+        const int ncol = term ? nx : nxu;
+        const float* Gm = term ? fp + I.oCN : fp + I.oG + (size_t)i * nc * nxu;
+        const int ldm = term ? nx : nxu;
+        lite_gemv_t(nr, ncol, Gm, ldm, V.wv, V.tv, V.part);
+        for (int j = t; j < ncol; j += kWG) {
+          const double q = rho * fabs((double)V.tv[j]);
+          rd = (q > rd || q != q) ? q : rd;
+        }
+        if (sigma_it) {
+          lite_gemv_t(nr, ncol, Gm, ldm, V.wv2, V.tv, V.part);
+          for (int j = t; j < ncol; j += kWG) gl = fmax(gl, rho * fabs((double)V.tv[j]));
+        }
+      }
+      lds_barrier();
+    }
+    mark(10);
+    if (term) break;
+    for (int j = t; j < nx; j += kWG) V.xz[j] = V.g2[j] + cst * P[pk.b + j];
+    sv = nv; sy = ny; sz = nz; sl = nl; su = nu_; sX = nX; sU = nU;
+    pk_dma_wait();
+    lds_barrier();
+    mark(11);
+    cb ^= 1;
+  }
+  rp = wg_max_d(rp, V.red);
+  rd = wg_max_d(rd, V.red);
+  if (sigma_it) {
+    vmax = wg_max_d(vmax, V.red);
+    zmax = wg_max_d(zmax, V.red);
+    gl = wg_max_d(gl, V.red);
+    hx = batch_hxi(Ip, ag, base);   // on the x, u just accumulated
+  }
+  LDS double* out = V.red + kWG;   // the reduction buffer holds kWG + 8 doubles
+  if (t == 0) { out[0] = rp; out[1] = rd; out[2] = vmax; out[3] = zmax; out[4] = hx; out[5] = gl; }
+  lds_barrier();
+}
+
 // ADMM iterations of one instance at fixed rho.  Returns 1 solved, 2 max_iter,
 // 3 numerical, 4 rho change (new rho in *rho_new).
 // it0: iteration count when this attempt (cold or warm start) began; the rho
 // rule runs every sigma iterations of the attempt.
-__device__ int batch_iterate(const BInst& I, const BatchArgs& a, double rho, int it0, int max_iter, int* it,
-                             double* rho_new, double* rp_out, double* rd_out, LDS char* base) {
-  const int N = I.N, nx = I.nx, nu = I.nu, nc = I.nc, nf = I.nf, nxu = nx + nu;
+__device__ __attribute__((noinline)) int batch_iterate(const BInst* __restrict__ Ip,
+                                                       const BatchArgs* __restrict__ ag, double rho, int it0,
+                                                       int max_iter, int* it, double* rho_new, double* rp_out,
+                                                       double* rd_out, LDS char* base) {
+  Ip = uniform_ptr(Ip);
+  ag = uniform_ptr(ag);
+  const BInst& I = *Ip;
+  const BatchArgs& a = *ag;
+  const int N = I.N, nx = I.nx, nu = I.nu, nc = I.nc, nf = I.nf;
   const BLayout lay = batch_layout(nx, nu, I.box ? 0 : (nc > nf ? nc : nf));
-  LDS float* F0 = (LDS float*)base;
-  LDS float* g = F0 + lay.vec;
-  LDS float* g2 = g + kBV;
-  LDS float* xz = g2 + kBV;
-  LDS float* tv = xz + kBV;
-  LDS float* tu = tv + kBV;
-  LDS float* wv = tu + kBV;
-  LDS float* wv2 = wv + kBV;
-  LDS float* part = wv2 + 2 * kBV;
-  LDS double* red = (LDS double*)(base + lay.red);
-  float* fp = a.fp;
-  double* dp = a.dp;
-  const float fr = (float)rho;
-  double* ys = dp + I.oy;
-  double* zs = dp + I.oz;
-  double* vacc = dp + I.ov;
-  double* wprev = dp + I.owp;
-  const double* ls = dp + I.ol;
-  const double* us = dp + I.ou;
-  double* X = dp + I.oX;
-  double* U = dp + I.oU;
-  float* kff = fp + I.okff;
-  const float* x0 = fp + I.ox0;
+  const IterVecs V = iter_vecs(lay, base);
+  const float* fp = a.fp;
+  double* ys = a.dp + I.oy;
+  const int t = tid();
+  if (a.prof && t < 16) V.pc[t] = 0ull;
   double hnorm = 0.0;
-  for (int t = tid(); t < (N + 1) * nx; t += kWG) hnorm = fmax(hnorm, fabs((double)fp[I.oq + t]));
-  for (int t = tid(); t < N * nu; t += kWG) hnorm = fmax(hnorm, fabs((double)fp[I.orr + t]));
-  hnorm = wg_max_d(hnorm, red);
+  for (int e = t; e < (N + 1) * nx; e += kWG) hnorm = fmax(hnorm, fabs((double)fp[I.oq + e]));
+  for (int e = t; e < N * nu; e += kWG) hnorm = fmax(hnorm, fabs((double)fp[I.orr + e]));
+  hnorm = wg_max_d(hnorm, V.red);
   bool first = true;
   while (true) {
     ++*it;
     const bool full = first;
-    const float cst = full ? 1.f : 0.f;
     const bool sigma_it = a.adaptive && ((*it - it0) % a.sigma == 0) && *it < max_iter;
-    // ---- backward: p_N = cst q_N + rho C_N^T dw_N
-    for (int r = tid(); r < nf; r += kWG) {
-      const size_t gr = (size_t)N * nc + r;
-      const double w = ys[gr] - zs[gr];
-      wv[r] = (float)(full ? w : w - wprev[gr]);
-      wprev[gr] = w;
-    }
-    __syncthreads();
-    if (nf > 0 && !I.box) wg_gemv_t<float, 20>(nf, nx, (const float*)(fp + I.oCN), nx, wv, tv, part, false);
-    for (int j = tid(); j < nx; j += kWG) {
-      const float cw = nf > 0 ? (I.box ? wv[j] : tv[j]) : 0.f;
-      g[j] = cst * fp[I.oq + (size_t)N * nx + j] + fr * cw;
-    }
-    __syncthreads();
-    for (int i = N - 1; i >= 0; --i) {
-      const float* Fi = fp + I.oF + (size_t)i * nxu * nxu;
-      // dw_i and [C^T w; D^T w]
-      for (int r = tid(); r < nc; r += kWG) {
-        const size_t gr = (size_t)i * nc + r;
-        const double w = ys[gr] - zs[gr];
-        wv[r] = (float)(full ? w : w - wprev[gr]);
-        wprev[gr] = w;
-      }
-      __syncthreads();
-      if (!I.box) {
-        if (nc > 0) {
-          wg_gemv_t<float, 16>(nc, nxu, (const float*)(fp + I.oG + (size_t)i * nc * nxu), nxu, wv, tv, part, false);
-        } else {
-          for (int j = tid(); j < nxu; j += kWG) tv[j] = 0.f;
-          __syncthreads();
-        }
-      }
-      // r_hat (tu), c = q_hat + ev + K^T r_hat (wv2)
-      for (int j = tid(); j < nu; j += kWG) {
-        const float gw = I.box ? wv[nx + j] : tv[nx + j];
-        tu[j] = cst * fp[I.orr + (size_t)i * nu + j] + fr * gw;
-      }
-      for (int j = tid(); j < nx; j += kWG) {
-        const float gw = I.box ? wv[j] : tv[j];
-        wv2[j] = cst * (fp[I.oq + (size_t)i * nx + j] + fp[I.oev + (size_t)i * nx + j]) + fr * gw;
-      }
-      __syncthreads();
-      wg_gemv_t<float, 8>(nu, nx, Fi + nx * nxu, nxu, tu, wv2, part, true);   // + K^T r_hat
-      // [Abar^T p; B^T p]
-      wg_gemv_t<float, 20>(nx, nxu, Fi, nxu, g, g2, part, false);
-      for (int j = tid(); j < nu; j += kWG) tu[j] = g2[nx + j] + tu[j] + cst * fp[I.ofv + (size_t)i * nu + j];
-      for (int j = tid(); j < nx; j += kWG) g[j] = g2[j] + wv2[j];
-      __syncthreads();
-      // k_i = -Gamma (B^T p + f + r_hat)
-      wg_gemv_t<float, 8>(nu, nu, (const float*)(fp + I.oGam + (size_t)i * nu * nu), nu, tu, g2, part, false);
-      for (int j = tid(); j < nu; j += kWG) kff[(size_t)i * nu + j] = -g2[j];
-      __syncthreads();
-    }
-    // ---- forward roll-out, projection, dual update, residuals
-    double rp = 0.0, rd = 0.0, vmax = 0.0, zmax = 0.0, hx = 0.0, gl = 0.0;
-    for (int j = tid(); j < nx; j += kWG) xz[j] = cst * x0[j];
-    __syncthreads();
-    for (int i = 0; i <= N; ++i) {
-      const bool term = (i == N);
-      const int nr = term ? nf : nc;
-      for (int j = tid(); j < nx; j += kWG) {
-        const size_t gi = (size_t)i * nx + j;
-        X[gi] = full ? (double)xz[j] : X[gi] + (double)xz[j];
-      }
-      if (!term) {
-        const float* Fi = fp + I.oF + (size_t)i * nxu * nxu;
-        for (int j = tid(); j < nu; j += kWG) xz[nx + j] = kff[(size_t)i * nu + j];
-        __syncthreads();
-        wg_gemv_n<float, 24>(nxu, nxu, Fi, nxu, xz, g2, part, false);   // [Abar x + B k; K x + k]
-        for (int j = tid(); j < nu; j += kWG) {
-          const float uu = g2[nx + j];
-          xz[nx + j] = uu;
-          const size_t gi = (size_t)i * nu + j;
-          U[gi] = full ? (double)uu : U[gi] + (double)uu;
-        }
-        __syncthreads();
-        if (I.box) {
-          for (int r = tid(); r < nc; r += kWG) wv[r] = xz[r];
-        } else if (nc > 0) {
-          wg_gemv_n<float, 24>(nc, nxu, (const float*)(fp + I.oG + (size_t)i * nc * nxu), nxu, xz, wv, part, false);
-        }
-      } else if (nr > 0) {
-        if (I.box) {
-          for (int r = tid(); r < nf; r += kWG) wv[r] = xz[r];
-        } else {
-          wg_gemv_n<float, 20>(nf, nx, (const float*)(fp + I.oCN), nx, xz, wv, part, false);
-        }
-      }
-      __syncthreads();
-      for (int r = tid(); r < nr; r += kWG) {
-        const size_t gr = (size_t)i * nc + r;
-        const double v = full ? (double)wv[r] : vacc[gr] + (double)wv[r];
-        vacc[gr] = v;
-        const double yo = ys[gr], zo = zs[gr];
-        const double t = v + yo;
-        const double zn = t < ls[gr] ? ls[gr] : (t > us[gr] ? us[gr] : t);
-        const double yn = yo + v - zn;
-        zs[gr] = zn;
-        ys[gr] = yn;
-        const double e = fabs(v - zn);
-        rp = (e > rp || e != e) ? e : rp;
-        vmax = fmax(vmax, fabs(v));
-        zmax = fmax(zmax, fabs(zn));
-        wv[r] = (float)(zn - zo);
-        wv2[r] = (float)yn;
-      }
-      __syncthreads();
-      if (nr > 0) {
-        if (I.box) {
-          for (int r = tid(); r < nr; r += kWG) {
-            const double q = rho * fabs((double)wv[r]);
-            rd = (q > rd || q != q) ? q : rd;
-            if (sigma_it) gl = fmax(gl, rho * fabs((double)wv2[r]));
-          }
-        } else {
-          const int ncol = term ? nx : nxu;
-          const float* Gm = term ? fp + I.oCN : fp + I.oG + (size_t)i * nc * nxu;
-          const int ldm = term ? nx : nxu;
-          wg_gemv_t<float, 16>(nr, ncol, Gm, ldm, wv, tv, part, false);
-          for (int j = tid(); j < ncol; j += kWG) {
-            const double q = rho * fabs((double)tv[j]);
-            rd = (q > rd || q != q) ? q : rd;
-          }
-          if (sigma_it) {
-            wg_gemv_t<float, 16>(nr, ncol, Gm, ldm, wv2, tv, part, false);
-            for (int j = tid(); j < ncol; j += kWG) gl = fmax(gl, rho * fabs((double)tv[j]));
-          }
-        }
-        __syncthreads();
-      }
-      if (sigma_it) {
-        // |H xi| on the accumulated iterate
-        for (int j = tid(); j < nx; j += kWG) tv[j] = (float)X[(size_t)i * nx + j];
-        if (!term)
-          for (int j = tid(); j < nu; j += kWG) tu[j] = (float)U[(size_t)i * nu + j];
-        __syncthreads();
-        wg_gemv_n<float, 20>(nx, nx, (const float*)(fp + I.oQ + (size_t)i * nx * nx), nx, tv, wv2, part, false);
-        if (!term) {
-          wg_gemv_t<float, 8>(nu, nx, (const float*)(fp + I.oS + (size_t)i * nu * nx), nx, tu, wv2, part, true);
-          wg_gemv_n<float, 8>(nu, nu, (const float*)(fp + I.oR + (size_t)i * nu * nu), nu, tu, g, part, false);
-          wg_gemv_n<float, 20>(nu, nx, (const float*)(fp + I.oS + (size_t)i * nu * nx), nx, tv, g, part, true);
-          for (int j = tid(); j < nu; j += kWG) hx = fmax(hx, fabs((double)g[j]));
-        }
-        for (int j = tid(); j < nx; j += kWG) hx = fmax(hx, fabs((double)wv2[j]));
-        __syncthreads();
-      }
-      if (term) break;
-      for (int j = tid(); j < nx; j += kWG) xz[j] = g2[j] + cst * fp[I.ob + (size_t)i * nx + j];
-      __syncthreads();
+    if (I.box) {
+      batch_backward<true>(Ip, ag, (float)rho, full, base);
+      batch_forward<true>(Ip, ag, rho, full, sigma_it, base);
+    } else {
+      batch_backward<false>(Ip, ag, (float)rho, full, base);
+      batch_forward<false>(Ip, ag, rho, full, sigma_it, base);
     }
     first = false;
-    rp = wg_max_d(rp, red);
-    rd = wg_max_d(rd, red);
+    LDS double* out = V.red + kWG;
+    const double rp = out[0], rd = out[1];
+    lds_barrier();
     *rp_out = rp;
     *rd_out = rd;
+    if (a.prof && t < 16) { atomicAdd(a.prof + t, V.pc[t]); V.pc[t] = 0ull; }
     if (rp != rp || rd != rd || isinf(rp) || isinf(rd)) return 3;
     if (rp <= a.tol && rd <= a.tol) return 1;
     if (*it >= max_iter) return 2;
     if (sigma_it) {
-      vmax = wg_max_d(vmax, red); zmax = wg_max_d(zmax, red);
-      hx = wg_max_d(hx, red); gl = wg_max_d(gl, red);
+      const double vmax = out[2], zmax = out[3], hx = out[4], gl = out[5];
       const double ps = fmax(vmax, zmax), ds = fmax(fmax(hx, gl), hnorm);
       const double ratio = (rp / (ps + 1e-10)) / (rd / (ds + 1e-10) + 1e-10);
       double rn = fmin(fmax(rho * sqrt(ratio), a.rho_min), a.rho_max);
       if (rn > rho * a.rho_tol || rn < rho / a.rho_tol) {
         const double f = rho / rn;
-        for (int r = tid(); r < I.m; r += kWG) ys[r] *= f;
-        __syncthreads();
+        for (int r = t; r < I.m; r += kWG) ys[r] *= f;
+        __syncthreads();   // cross-thread global update: full fence
         *rho_new = rn;
         return 4;
       }
@@ -430,10 +729,11 @@ __device__ int batch_iterate(const BInst& I, const BatchArgs& a, double rho, int
   }
 }
 
-__global__ void __launch_bounds__(kWG) k_batch(BatchArgs a) {
+__global__ void __launch_bounds__(kWG) k_batch(const BatchArgs* __restrict__ ag) {
   extern __shared__ __align__(16) char lds_generic[];
   LDS char* base = (LDS char*)lds_generic;
   __shared__ unsigned s_item;
+  const BatchArgs& a = *ag;
   while (true) {
     if (tid() == 0) s_item = atomicAdd(a.counter, 1u);
     __syncthreads();
@@ -441,21 +741,28 @@ __global__ void __launch_bounds__(kWG) k_batch(BatchArgs a) {
     __syncthreads();
     if (item >= (unsigned)a.count) break;
     const int idx = a.order[item];
-    const BInst I = a.inst[idx];
+    const BInst* Ip = a.inst + idx;
+    const int m = Ip->m;
+    const long long oz = Ip->oz, oy = Ip->oy;
     bool warm = a.warm[idx] != 0;
     if (!warm)
-      for (int r = tid(); r < I.m; r += kWG) { a.dp[I.oz + r] = 0.0; a.dp[I.oy + r] = 0.0; }
+      for (int r = tid(); r < m; r += kWG) { a.dp[oz + r] = 0.0; a.dp[oy + r] = 0.0; }
     __syncthreads();
     double rho = a.rho0[idx];
     int it = 0, nupd = 0, nfact = 0, st = 0, restarted = 0;
     double rp = 0.0, rd = 0.0;
     const bool budgeted = warm && a.warm_budget > 0 && a.warm_budget < a.max_iter;
     int limit = budgeted ? a.warm_budget : a.max_iter, it0 = 0;
+    long long te = 0, ti = 0;
     while (true) {
       ++nfact;
-      if (!batch_epoch(I, a, rho, base)) { st = -1; break; }
+      const long long c0 = wall_clock64();
+      if (!batch_epoch(Ip, ag, rho, base)) { st = -1; break; }
+      const long long c1 = wall_clock64();
       double rn = rho;
-      st = batch_iterate(I, a, rho, it0, limit, &it, &rn, &rp, &rd, base);
+      st = batch_iterate(Ip, ag, rho, it0, limit, &it, &rn, &rp, &rd, base);
+      te += c1 - c0;
+      ti += wall_clock64() - c1;
       if (st == 4) { rho = rn; ++nupd; continue; }
       if (warm && budgeted && (st == 2 || st == 3)) {
         // the warm start did not pay off: restart from z = y = 0 with a
@@ -465,7 +772,7 @@ __global__ void __launch_bounds__(kWG) k_batch(BatchArgs a) {
         it0 = it;
         limit = it + a.max_iter;
         rho = a.rho_cold;
-        for (int r = tid(); r < I.m; r += kWG) { a.dp[I.oz + r] = 0.0; a.dp[I.oy + r] = 0.0; }
+        for (int r = tid(); r < m; r += kWG) { a.dp[oz + r] = 0.0; a.dp[oy + r] = 0.0; }
         __syncthreads();
         continue;
       }
@@ -476,6 +783,7 @@ __global__ void __launch_bounds__(kWG) k_batch(BatchArgs a) {
       r.status = st; r.iterations = it; r.rho_updates = nupd; r.factorizations = nfact;
       r.restarted = restarted;
       r.r_p = rp; r.r_d = rd; r.rho = rho;
+      r.t_epoch = te; r.t_iter = ti;
       a.res[idx] = r;
     }
     __syncthreads();
@@ -563,8 +871,16 @@ int batch_setup(const gsls_qp_desc* descs, int count, const gsls_settings* s, hi
       I.oG = 0; I.oCN = 0;
     }
     I.ox0 = reservef(nx);
-    I.oF = reservef(N * nxu * nxu); I.oGam = reservef(N * nu * nu);
-    I.oev = reservef(N * nx); I.ofv = reservef(N * nu); I.okff = reservef(N * nu);
+    const PkLayout pk = pk_layout(d.nx, d.nu);
+    if (pk.stride > kPkVec * 4 * kWG) return GSLS_ERR_DIM;
+    I.oPk = reservef(N * (size_t)pk.stride);
+    for (size_t k = 0; k < N; ++k) {   // constant stage data of the packets
+      float* pp = fpool.data() + I.oPk + k * pk.stride;
+      for (size_t j = 0; j < nx; ++j) pp[pk.q + j] = d.q ? (float)d.q[k * nx + j] : 0.f;
+      for (size_t j = 0; j < nu; ++j) pp[pk.r + j] = d.r ? (float)d.r[k * nu + j] : 0.f;
+      for (size_t j = 0; j < nx; ++j) pp[pk.b + j] = d.b ? (float)d.b[k * nx + j] : 0.f;
+    }
+    I.okff = reservef(N * nu);
     I.ol = pushd(d.l, I.m); I.ou = pushd(d.u, I.m);
     I.oz = reserved(I.m); I.oy = reserved(I.m); I.ov = reserved(I.m); I.owp = reserved(I.m);
     I.oX = reserved((N + 1) * nx); I.oU = reserved(N * nu);
@@ -585,6 +901,7 @@ int batch_setup(const gsls_qp_desc* descs, int count, const gsls_settings* s, hi
   if (hipMalloc(&B->d_warm, count * sizeof(int)) != hipSuccess) return GSLS_ERR_OOM;
   if (hipMalloc(&B->d_res, count * sizeof(BResult)) != hipSuccess) return GSLS_ERR_OOM;
   if (hipMalloc(&B->d_counter, sizeof(unsigned)) != hipSuccess) return GSLS_ERR_OOM;
+  if (hipMalloc(&B->d_args, sizeof(BatchArgs)) != hipSuccess) return GSLS_ERR_OOM;
   if (hipMemcpy(B->fp, fpool.data(), B->nfp * 4, hipMemcpyHostToDevice) != hipSuccess) return GSLS_ERR_HIP;
   if (hipMemcpy(B->dp, dpool.data(), B->ndp * 8, hipMemcpyHostToDevice) != hipSuccess) return GSLS_ERR_HIP;
   if (hipMemcpy(B->d_inst, B->inst.data(), count * sizeof(BInst), hipMemcpyHostToDevice) != hipSuccess)
@@ -648,21 +965,25 @@ int batch_run(BatchSolver* B, double tol, int warm_budget, gsls_result* out, dou
   a.rho_min = B->st.rho_min; a.rho_max = B->st.rho_max; a.rho_tol = B->st.rho_tol;
   a.res = B->d_res; a.counter = B->d_counter; a.warm = B->d_warm;
   a.warm_budget = warm_budget; a.rho_cold = 1.0;
+  a.prof = B->d_prof;
+  if (hipMemcpyAsync(B->d_args, &a, sizeof(a), hipMemcpyHostToDevice, B->stream) != hipSuccess) return GSLS_ERR_HIP;
   // the launch (counter reset by a fill kernel, then the persistent solver) is
   // captured once per (tol, warm budget) into a graph and replayed
-  if (!B->gexec || B->graph_key[0] != tol || B->graph_key[1] != (double)warm_budget) {
+  const double pkey = B->d_prof ? 1.0 : 0.0;
+  if (!B->gexec || B->graph_key[0] != tol || B->graph_key[1] != (double)warm_budget || B->graph_key[2] != pkey) {
     if (B->gexec) { (void)hipGraphExecDestroy(B->gexec); B->gexec = nullptr; }
     if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
     hipStream_t cs;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return GSLS_ERR_HIP;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return GSLS_ERR_HIP;
     k_zero_u32<<<1, 1, 0, cs>>>(B->d_counter);
-    k_batch<<<B->grid, kWG, B->lds, cs>>>(a);
+    k_batch<<<B->grid, kWG, B->lds, cs>>>(B->d_args);
     if (hipStreamEndCapture(cs, &B->graph) != hipSuccess) return GSLS_ERR_HIP;
     (void)hipStreamDestroy(cs);
     if (hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0) != hipSuccess) return GSLS_ERR_HIP;
     B->graph_key[0] = tol;
     B->graph_key[1] = (double)warm_budget;
+    B->graph_key[2] = pkey;
   }
   if (hipEventRecord(B->e0, B->stream) != hipSuccess) return GSLS_ERR_HIP;
   if (hipGraphLaunch(B->gexec, B->stream) != hipSuccess) return GSLS_ERR_HIP;
@@ -682,6 +1003,8 @@ int batch_run(BatchSolver* B, double tol, int warm_budget, gsls_result* out, dou
     r.status = b.status == 1 ? GSLS_SOLVED : (b.status == 2 ? GSLS_MAX_ITER : GSLS_NUMERICAL_FAIL);
     r.iterations = b.iterations; r.rho_updates = b.rho_updates; r.factorizations = b.factorizations;
     r.r_p = b.r_p; r.r_d = b.r_d; r.rho = b.rho; r.ms_total = t;
+    r.ms_factor = (double)b.t_epoch * 1e-5;    // 100 MHz counter -> ms (this instance's workgroup)
+    r.ms_iterate = (double)b.t_iter * 1e-5;
     r.cold_restart = b.restarted;
     out[c] = r;
   }
@@ -776,5 +1099,26 @@ int gsls_batch_get(gsls_batch* b, int32_t index, double* X, double* U, double* z
 }
 
 void gsls_batch_free(gsls_batch* b) { delete b; }
+
+int gsls_batch_debug_phase_cycles(gsls_batch* b, int32_t enable, double* cycles16) {
+  if (!b) return GSLS_ERR_INVALID_ARG;
+  gsls::BatchSolver* B = &b->s;
+  if (cycles16) {
+    for (int i = 0; i < 16; ++i) cycles16[i] = 0.0;
+    if (B->d_prof) {
+      unsigned long long h[16];
+      if (hipMemcpy(h, B->d_prof, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return GSLS_ERR_HIP;
+      for (int i = 0; i < 16; ++i) cycles16[i] = (double)h[i];
+    }
+  }
+  if (enable && !B->d_prof) {
+    if (hipMalloc(&B->d_prof, 16 * sizeof(unsigned long long)) != hipSuccess) return GSLS_ERR_OOM;
+  } else if (!enable && B->d_prof) {
+    (void)hipFree(B->d_prof);
+    B->d_prof = nullptr;
+  }
+  if (B->d_prof && hipMemset(B->d_prof, 0, 16 * sizeof(unsigned long long)) != hipSuccess) return GSLS_ERR_HIP;
+  return GSLS_OK;
+}
 
 }  // extern "C"

@@ -12,13 +12,14 @@ namespace gsls {
 struct BInst {
   int N, nx, nu, nc, nf, box, m;
   long long oA, oB, ob, oQ, oR, oS, oq, orr, oG, oCN, ox0;  // float pool: problem
-  long long oF, oGam, oev, ofv, okff;                      // float pool: epoch outputs, gains
+  long long oPk, okff;                                     // float pool: stage packets, feed-forward k
   long long ol, ou, oz, oy, ov, owp, oX, oU;                // double pool
 };
 
 struct BResult {
   int status, iterations, rho_updates, factorizations, restarted;
   double r_p, r_d, rho;
+  long long t_epoch, t_iter;   // device clock ticks (100 MHz real-time counter)
 };
 
 struct BatchArgs {
@@ -37,6 +38,7 @@ struct BatchArgs {
   int warm_budget;             // > 0: a warm start that has not converged after
                                // this many iterations restarts cold
   double rho_cold;             // rho of such a cold restart
+  unsigned long long* prof;    // [16] phase clock counters, or null
 };
 
 struct BatchSolver {
@@ -55,21 +57,24 @@ struct BatchSolver {
   int* d_warm = nullptr;
   BResult* d_res = nullptr;
   unsigned* d_counter = nullptr;
+  BatchArgs* d_args = nullptr;    // kernel arguments (the graph keeps this pointer)
   int grid = 0;
   // feature rows of the learned warm start: one per stage k = 0..N of every
   // instance, instance c owning rows row_off[c] .. row_off[c+1]-1
+  unsigned long long* d_prof = nullptr;   // phase counters when profiling is on
   std::vector<int> row_off;
   int* d_row_inst = nullptr;   // [rows] owning instance
   int* d_row_off = nullptr;    // [count + 1]
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  double graph_key[2] = {-1, -1};   // (tol, warm budget) the graph was captured for
+  double graph_key[3] = {-1, -1, -1};   // (tol, warm budget, profiling) of the captured graph
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ~BatchSolver() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     for (void* p : {(void*)fp, (void*)dp, (void*)d_inst, (void*)d_order, (void*)d_rho, (void*)d_warm,
-                    (void*)d_res, (void*)d_counter, (void*)d_row_inst, (void*)d_row_off})
+                    (void*)d_res, (void*)d_counter, (void*)d_row_inst, (void*)d_row_off, (void*)d_prof,
+                    (void*)d_args})
       if (p) (void)hipFree(p);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

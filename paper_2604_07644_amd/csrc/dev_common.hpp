@@ -25,6 +25,35 @@ constexpr unsigned kSpinLimit = 1u << 22;   // bounded waits (a few seconds): gi
 
 __device__ __forceinline__ int tid() { return threadIdx.x; }
 
+// Global-memory address space: loads and stores through such pointers are
+// global_* instructions (counted by vmcnt only), not flat ones (which also
+// count against lgkmcnt and so make every LDS wait wait for them too).
+#define GLB __attribute__((address_space(1)))
+
+// A pointer known to be the same in every lane (e.g. a device function
+// argument derived from kernel arguments) moved to scalar registers, so that
+// address arithmetic on it stays scalar and buffer descriptors built from it
+// need no per-lane loop.
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (T*)(((unsigned long long)hi << 32) | lo);
+}
+
+// Workgroup barrier that orders LDS only: waits for the thread's own LDS
+// operations, then s_barrier.  Unlike __syncthreads() it does not wait for
+// outstanding global loads and stores, so prefetches stay in flight and
+// stores drain in the background.  Valid only where every global location a
+// thread reads after the barrier was written by that same thread (or before
+// the kernel began); cross-thread global data needs __syncthreads().
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------------------------ GEMM
 // C = alpha * op(A) * op(B) + beta * C, with op(A) m x k and op(B) k x n.
 //   A element (i, t) = ta ? A[t*lda + i] : A[i*lda + t]

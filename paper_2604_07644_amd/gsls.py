@@ -88,6 +88,7 @@ def _load():
                                            ct.POINTER(Result), _dp]),
         "gsls_batch_get": (ct.c_int, [P, ct.c_int32, _dp, _dp, _dp, _dp]),
         "gsls_batch_free": (None, [P]),
+        "gsls_batch_debug_phase_cycles": (ct.c_int, [P, ct.c_int32, _dp]),
         "gsls_ws_nparams": (ct.c_int64, []),
         "gsls_ws_create": (ct.c_int, [_fp, _fp, P, ct.POINTER(P)]),
         "gsls_ws_get_params": (ct.c_int, [P, _fp]),
@@ -313,6 +314,15 @@ class Batch:
         n = len(self.probs)
         x0s = [_f64(p.x0) for p in self.probs] if x0s is None else [_f64(x) for x in x0s]
         return x0s, (_dp * n)(*[_ptr(x) for x in x0s])
+
+    def phase_cycles(self, enable=True):
+        """Per-phase device clock counters of the iterations since the last
+        call (gsls_batch_debug_phase_cycles); enable keeps counting."""
+        out = np.zeros(16)
+        rc = lib.gsls_batch_debug_phase_cycles(self.h, int(enable), _ptr(out))
+        if rc != OK:
+            raise GslsError(rc, "gsls_batch_debug_phase_cycles")
+        return out
 
     def rows(self):
         """Number of warm-start feature rows (sum of N + 1)."""

@@ -55,14 +55,18 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 // ------------------------------------------------------------------ GEMM
+// Reductions up to this many K-slabs have all their loads issued at once.
+constexpr int kGemmSlabsInFlight = 5;
+
 // C = alpha * op(A) * op(B) + beta * C, with op(A) m x k and op(B) k x n.
 //   A element (i, t) = ta ? A[t*lda + i] : A[i*lda + t]
 //   B element (t, j) = tb ? B[j*ldb + t] : B[t*ldb + j]
 // Thread (ty, tx) of a 16 x 16 grid owns rows ty + 16a and columns tx + 16b of
 // C (a, b < TT).  op(A) and op(B) pass through LDS in K-slabs of kKT; each
-// thread holds TT elements of each slab in registers, and the next slab's
-// loads are issued before the current slab is multiplied, so global latency
-// overlaps the arithmetic.  Indices are clamped into range (loads never leave
+// thread holds TT elements of each slab in registers.  For k up to
+// kGemmSlabsInFlight slabs all loads are issued before the first product (a
+// single global latency per product); beyond that the next slab's loads
+// overlap the current product.  Indices are clamped into range (loads never leave
 // the operand) and out-of-range terms masked to zero.  beta == 0 never reads
 // C.  All reads of A and B complete before C is written, so C may alias them.
 // smem: 2 * 16*TT * kKT elements.
@@ -70,6 +74,7 @@ template <typename T, int TT>
 __device__ void wg_gemm_tt(int m, int n, int k, T alpha, const T* A, int lda, bool ta,
                            const T* B, int ldb, bool tb, T beta, T* C, int ldc, LDS T* smem) {
   constexpr int MM = 16 * TT;
+  constexpr int NS = kGemmSlabsInFlight;
   LDS T* As = smem;              // [MM][kKT]
   LDS T* Bs = smem + MM * kKT;   // [kKT][MM]
   const int tx = tid() & 15, ty = tid() >> 4;
@@ -78,8 +83,7 @@ __device__ void wg_gemm_tt(int m, int n, int k, T alpha, const T* A, int lda, bo
   for (int a = 0; a < TT; ++a)
 #pragma unroll
     for (int b = 0; b < TT; ++b) acc[a][b] = T(0);
-  T ra[TT], rb[TT];
-  auto load = [&](int t0) {
+  auto load = [&](int t0, T* ra, T* rb) {
 #pragma unroll
     for (int q = 0; q < TT; ++q) {
       const int e = tid() + q * kWG;
@@ -97,8 +101,7 @@ __device__ void wg_gemm_tt(int m, int n, int k, T alpha, const T* A, int lda, bo
       rb[q] = (j < n && t0 + t < k) ? v : T(0);
     }
   };
-  load(0);
-  for (int t0 = 0; t0 < k; t0 += kKT) {
+  auto multiply = [&](const T* ra, const T* rb) {
 #pragma unroll
     for (int q = 0; q < TT; ++q) {
       const int e = tid() + q * kWG;
@@ -106,7 +109,6 @@ __device__ void wg_gemm_tt(int m, int n, int k, T alpha, const T* A, int lda, bo
       Bs[e] = rb[q];
     }
     __syncthreads();
-    if (t0 + kKT < k) load(t0 + kKT);
     // slabs are zero-padded past k, so the slab loop has a fixed trip count
 #pragma unroll
     for (int t = 0; t < kKT; ++t) {
@@ -121,6 +123,26 @@ __device__ void wg_gemm_tt(int m, int n, int k, T alpha, const T* A, int lda, bo
         for (int b = 0; b < TT; ++b) acc[a][b] += av[a] * bv[b];
     }
     __syncthreads();
+  };
+  if (k <= NS * kKT) {
+    // every slab's loads are issued up front: one global latency per product
+    T ra[NS][TT], rb[NS][TT];
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl)
+      if (sl * kKT < k) load(sl * kKT, ra[sl], rb[sl]);
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl)
+      if (sl * kKT < k) multiply(ra[sl], rb[sl]);
+  } else {
+    // longer reductions: the next slab's loads overlap the current product
+    T ra[TT], rb[TT], na[TT], nb[TT];
+    load(0, ra, rb);
+    for (int t0 = 0; t0 < k; t0 += kKT) {
+      if (t0 + kKT < k) load(t0 + kKT, na, nb);
+      multiply(ra, rb);
+#pragma unroll
+      for (int q = 0; q < TT; ++q) { ra[q] = na[q]; rb[q] = nb[q]; }
+    }
   }
 #pragma unroll
   for (int a = 0; a < TT; ++a) {

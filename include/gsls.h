@@ -255,7 +255,7 @@ int gsls_batch_debug_phase_cycles(gsls_batch* b, int32_t enable, double* cycles1
  * MLP 160-512-512-512-192, ReLU on the hidden layers; parameters are one flat
  * FP32 vector W1 (160 x 512 row-major), b1, W2, b2, W3, b3, W4, b4; BF16
  * copies feed the matrix cores (FP32 accumulation); Adam keeps FP32 master
- * weights.  Loss sum(M (Y - T)^2) / sum(M).
+ * weights.  Loss sum(M (Y - T)^2) / sum(M), M the per-entry weights.
  *
  * Device pointers (X, T, M, idx, Y) are device memory; work runs on the
  * handle's stream (gsls_ws_create) or the batch's stream (batch calls).
@@ -299,8 +299,9 @@ int32_t gsls_ws_batch_rows(gsls_batch* b);
  * uploaded) into device X[rows][160]. */
 int gsls_ws_features(gsls_ws* h, gsls_batch* b, const double* const* x0, uint16_t* X);
 
-/* Target rows and mask (device FP32 [rows][192]) from the batch's last
- * solution: z, lambda = rho y and log10 of each instance's final rho. */
+/* Target rows and loss weights (device FP32 [rows][192]) from the batch's
+ * last solution: z, lambda = rho y (weight 1) and log10 of each instance's
+ * final rho (weight 25); other entries weight 0. */
 int gsls_ws_targets(gsls_batch* b, float* T, float* M);
 
 /* Learned warm start + batched solve: features, MLP, start (rho0 =

@@ -21,12 +21,13 @@ of the first state row and u_max that of the first input row:
 Target row (d_out = 192): z of the stage's state rows / x_max in [0:nx],
 input rows / u_max in [75:75+nu], lambda = rho y of the state rows in
 [94:94+nx], input rows in [169:169+nu], log10 of the solver's final rho in
-[188]; the mask is 1 exactly on these entries.
+[188]; the mask (a loss weight) is 1 on the z and lambda entries and
+RHO_WEIGHT on the rho entry, 0 elsewhere.
 
 MLP: h1 = relu(X W1 + b1), h2 = relu(h1 W2 + b2), h3 = relu(h2 W3 + b3),
 Y = h3 W4 + b4, sizes 160-512-512-512-192.  Parameters are one flat vector in
 the order W1 (d_in x d_out, row-major), b1, W2, b2, W3, b3, W4, b4.
-Loss  L = sum(M * (Y - T)^2) / sum(M).
+Loss  L = sum(M * (Y - T)^2) / sum(M)  (M: per-entry weights).
 Adam (Kingma & Ba, 2015) with bias correction:
     m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
     theta -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
@@ -39,6 +40,7 @@ SIZES = (160, 512, 512, 512, 192)
 D_IN, D_OUT = 160, 192
 XS, US = 75, 19           # state / input slots of the padded layouts
 RHO_COL = 188
+RHO_WEIGHT = 25.0         # loss weight of the rho entry (one entry per row vs up to 188 others)
 
 
 def n_params(sizes=SIZES):
@@ -161,7 +163,7 @@ def targets(p, z, lam, rho):
         elif p.nf:
             T[k, :nx] = z[N * nc:] / xm; T[k, 94:94 + nx] = lam[N * nc:]
             M[k, :nx] = M[k, 94:94 + nx] = 1.0
-        T[k, RHO_COL] = np.log10(rho); M[k, RHO_COL] = 1.0
+        T[k, RHO_COL] = np.log10(rho); M[k, RHO_COL] = RHO_WEIGHT
     return T, M
 
 

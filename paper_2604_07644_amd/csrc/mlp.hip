@@ -36,6 +36,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kDin = 160, kDh = 512, kDout = 192, kLayers = 4;
 constexpr int kSketch = 64, kSlots = 94, kXs = 75, kUs = 19, kRhoCol = 188;
+constexpr float kRhoWeight = 25.f;   // loss weight of the rho entry of a row
 constexpr int kSizes[kLayers + 1] = {kDin, kDh, kDh, kDh, kDout};
 
 // round to nearest even (NaN kept quiet)
@@ -331,7 +332,8 @@ __global__ void __launch_bounds__(256) k_ws_scatter(const BInst* inst, double* d
   if (tid() == 0) { rho0[c] = rho; warm[c] = 1; }
 }
 
-// Targets and mask rows of instance c from its solution (z, y) and final rho.
+// Target and weight rows of instance c from its solution (z, y) and final
+// rho: weight 1 on the z and lambda entries, kRhoWeight on the rho entry.
 __global__ void __launch_bounds__(256) k_ws_targets(const BInst* inst, const double* dp, const int* row_off,
                                                     const BResult* res, float* T, float* Mk) {
   const int c = blockIdx.x;
@@ -357,7 +359,7 @@ __global__ void __launch_bounds__(256) k_ws_targets(const BInst* inst, const dou
       t = lam ? (float)(rho * yv) : (float)(zv / (j < nx ? xm : um));
       m = 1.f;
     }
-    if (col == kRhoCol) { t = lr; m = 1.f; }
+    if (col == kRhoCol) { t = lr; m = kRhoWeight; }
     T[(long long)(r0 + k) * kDout + col] = t;
     Mk[(long long)(r0 + k) * kDout + col] = m;
   }

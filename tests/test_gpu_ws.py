@@ -200,3 +200,32 @@ def test_save_load_round_trip(tmp_path):
     with pytest.raises(gsls.GslsError):
         gsls.WarmStart(path=bad)
     ws.close(); ws2.close()
+
+
+def test_trained_model_gain_on_held_out_batch():
+    """What the trained network (paper_2604_07644_amd/data/ws_box.bin) gains
+    over cold-start ADMM on 96 held-out instances (ids 600..695: disjoint from
+    the training ids >= 10^6 and the benchmark's 0..511): the same optimum
+    (each solve stops at r_p, r_d <= 1e-5, so the two solutions agree to a
+    few times the stopping error), and fewer iterations on the typical
+    instance (median)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2604_07644_amd", "data", "ws_box.bin")
+    ws = gsls.WarmStart(path=path)
+    probs = W.uneven_batch(count=96, first_instance=600, nmin=16, nmax=200)
+    b = gsls.Batch(probs)
+    cold, ms_c = b.solve(tol=1e-5)
+    xs = [b.get(i)["X"] for i in range(len(probs))]
+    warm, ms_w, ms_p = b.solve_ws(ws, tol=1e-5)
+    it_c = np.array([r["iterations"] for r in cold])
+    it_w = np.array([r["iterations"] for r in warm])
+    print(f"cold: median {np.median(it_c)} mean {it_c.mean():.1f} max {it_c.max()} ({ms_c:.1f} ms); "
+          f"warm: median {np.median(it_w)} mean {it_w.mean():.1f} max {it_w.max()} ({ms_w:.1f} ms, "
+          f"prediction {ms_p:.2f} ms)")
+    for i in range(len(probs)):
+        assert cold[i]["status"] == gsls.SOLVED and warm[i]["status"] == gsls.SOLVED
+        g = b.get(i)["X"]
+        assert np.max(np.abs(g - xs[i])) <= 5e-4 * max(np.max(np.abs(xs[i])), 1.0), i
+    assert np.median(it_w) < np.median(it_c), (np.median(it_w), np.median(it_c))
+    b.close(); ws.close()

@@ -116,7 +116,7 @@ def test_targets_and_warm_start_round_trip():
     z = np.clip(rng.standard_normal(p.m), p.l, p.u)
     lam = rng.standard_normal(p.m)
     T, M = mlp.targets(p, z, lam, rho=3.0)
-    assert int(M.sum()) == 2 * p.m + (p.N + 1)
+    assert M.sum() == 2 * p.m + (p.N + 1) * mlp.RHO_WEIGHT
     z0, y0, rho = mlp.warm_start(p, T)
     assert rho == pytest.approx(3.0, rel=1e-14)
     np.testing.assert_allclose(z0, z, rtol=1e-14, atol=1e-15)

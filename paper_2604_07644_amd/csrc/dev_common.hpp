@@ -1,8 +1,9 @@
 // Device building blocks shared by the gfx950 kernels: workgroup GEMM on
-// register micro-tiles, FP64 LU with partial pivoting and triangular solves in
-// LDS, FP64 Cholesky for the small control-dimension factors, workgroup
-// matrix-transpose-times-vector, and the packed (payload, stamp) words used
-// for low-latency exchange between workgroups of a persistent kernel.
+// register micro-tiles, FP32 MFMA products of LDS operands, FP64 Gauss-Jordan
+// elimination held in registers (partial pivoting, or none for symmetric
+// positive definite systems), workgroup matrix-vector products, and the
+// packed (payload, stamp) words used for low-latency exchange between
+// workgroups of a persistent kernel.
 //
 // All routines with the prefix wg_ must be called by every thread of the
 // workgroup (they contain __syncthreads); the workgroup size is kWG threads.
@@ -260,82 +261,172 @@ __device__ inline void wg_row_norms(int m, int n, const LDS float* M, int ld, in
   }
 }
 
-// -------------------------------------------------- FP64 Gauss-Jordan inverse
-constexpr int kGJRows = kMaxNx / 4;   // rows per wave
+// -------------------------------------------------- FP64 Gauss-Jordan elimination
 // Gauss-Jordan elimination of Aug = [M | R] (LDS, FP64, n x ld row-major,
 // ld = n + r, the caller fills both parts): on success the right part holds
-// M^{-1} R up to the row permutation perm and the row scales 1/dg, i.e.
-// (M^{-1} R)[j][c] = Aug[perm[j]][n + c] / dg[j] (read with wg_gj_extract).
-// Column j's pivot is the largest |entry| among rows not used as pivots yet
-// (pivot = true), or simply row j (pivot = false: for symmetric positive
-// definite M, where every pivot must then be positive; a non-positive pivot
-// is reported as failure).  Rows are never swapped and the pivot rows are
-// normalised at the end (elimination and row scaling commute).  Two barriers
-// per column.  Returns false uniformly on a zero, negative (SPD mode) or
-// non-finite pivot.  used: LDS int[n]; perm: LDS int[n]; dg: LDS double[n].
-__device__ inline bool wg_gj_eliminate(int n, int ld, LDS double* Aug, bool pivot, LDS int* perm, LDS int* used,
-                                       LDS double* dg) {
-  __shared__ int s_piv, s_bad;
-  const int lane = tid() & 63, w = tid() >> 6;
-  for (int r = tid(); r < n; r += kWG) used[r] = 0;
-  if (tid() == 0) s_bad = 0;
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    if (w == 0) {
-      double best = -1.0;
-      int bi = n;
-      if (pivot) {
-        for (int r = lane; r < n; r += 64) {
-          double v = fabs(Aug[r * ld + j]);
-          if (!used[r] && (v > best || (v == best && r < bi))) { best = v; bi = r; }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-          double ob = __shfl_xor(best, off, 64);
-          int oi = __shfl_xor(bi, off, 64);
-          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
-      } else {
-        bi = j;
-        best = Aug[j * ld + j];
-      }
-      if (lane == 0) {
-        s_piv = bi;
-        perm[j] = bi;
-        if (bi < n) used[bi] = 1;
-        if (!(best > 0.0) || !isfinite(best) || bi >= n) s_bad = 1;
-      }
-    }
-    __syncthreads();
-    if (s_bad) return false;
-    const int p = s_piv;
-    const double inv = 1.0 / Aug[p * ld + j];
-    const LDS double* prow = Aug + p * ld;
-    // eliminate column j from every other row (columns > j of both parts):
-    // the wave's multipliers, then per 64-column slot all its rows' entries,
-    // are loaded before any is updated, so LDS latency is paid once per slot
-    double mult[kGJRows];
+// M^{-1} R up to the row permutation perm and the row scales dg, i.e.
+// (M^{-1} R)[j][c] = Aug[perm[j]][n + c] * dg[j] (read with wg_gj_extract).
+// Column j's pivot is the largest |entry| among rows not used as pivots yet,
+// the lowest such row on ties (pivot = true), or simply row j (pivot = false:
+// for symmetric positive definite M, where every pivot must then be
+// positive).  Rows are never swapped and the pivot rows are normalised at the
+// end (elimination and row scaling commute).  Returns false uniformly on a
+// zero, negative (SPD mode) or non-finite pivot.  perm: LDS int[n];
+// dg: LDS double[n]; used: unused (kept for the callers' layouts).
+//
+// The matrix lives in registers for the whole elimination: lane l holds rows
+// l and l + 64 (RS slots), wave w holds columns w + 4k (KC slots).  Column j
+// is owned by one wave; while step j - 1 updates it, that wave also copies it
+// into an LDS vector (double-buffered by step parity), so the owner can pick
+// the pivot from it and every thread reads its row's multiplier from it after
+// the step's single (LDS-only) barrier.  The pivot row is broadcast inside
+// each wave with readlane, and the update is one FMA per register:
+//   a[r][c] -= (a[r][j] / a[p][j]) * a[p][c]   for r != p
+// (applied to every column: those up to j are dead and never read again).
+// The pivot search compares |a[r][j]| rounded to FP32 (a monotone key), so
+// among candidates equal at that precision the lowest row is taken.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Maximum of an unsigned key over the 64 lanes of the wave: a butterfly
+// inside each row of 16 lanes (quad swaps 1 and 2, half-row and row mirrors),
+// then the four row results combined on the scalar unit.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned k) {
+  k = max(k, (unsigned)__builtin_amdgcn_update_dpp(0, (int)k, 0xB1, 0xF, 0xF, true));
+  k = max(k, (unsigned)__builtin_amdgcn_update_dpp(0, (int)k, 0x4E, 0xF, 0xF, true));
+  k = max(k, (unsigned)__builtin_amdgcn_update_dpp(0, (int)k, 0x141, 0xF, 0xF, true));
+  k = max(k, (unsigned)__builtin_amdgcn_update_dpp(0, (int)k, 0x140, 0xF, 0xF, true));
+  const unsigned r0 = (unsigned)__builtin_amdgcn_readlane((int)k, 0);
+  const unsigned r1 = (unsigned)__builtin_amdgcn_readlane((int)k, 16);
+  const unsigned r2 = (unsigned)__builtin_amdgcn_readlane((int)k, 32);
+  const unsigned r3 = (unsigned)__builtin_amdgcn_readlane((int)k, 48);
+  return max(max(r0, r1), max(r2, r3));
+}
+
+template <int RS, int KC>
+__device__ __forceinline__ bool gj_eliminate_regs(int n, int ld, LDS double* Aug, bool pivot, LDS int* perm,
+                                                  LDS double* dg, LDS int* s_piv, LDS double* s_inv) {
+  const int l = lane();
+  const int w = __builtin_amdgcn_readfirstlane(wave());
+  double a[RS][KC];
+  __syncthreads();   // the caller's fill of Aug
 #pragma unroll
-    for (int k = 0; k < kGJRows; ++k) {
-      const int r = min(w + 4 * k, n - 1);
-      mult[k] = Aug[r * ld + j] * inv;
-    }
-    for (int c = j + 1 + lane; c < ld; c += 64) {
-      const double pv = prow[c];
-      double v[kGJRows];
+  for (int s = 0; s < RS; ++s)
 #pragma unroll
-      for (int k = 0; k < kGJRows; ++k) v[k] = Aug[min(w + 4 * k, n - 1) * ld + c];
-#pragma unroll
-      for (int k = 0; k < kGJRows; ++k) {
-        const int r = w + 4 * k;
-        const double nv = v[k] - mult[k] * pv;
-        if (r < n && r != p) Aug[r * ld + c] = nv;
-      }
+    for (int k = 0; k < KC; ++k) {
+      const int r = l + 64 * s, c = w + 4 * k;
+      a[s][k] = (r < n && c < ld) ? Aug[r * ld + c] : 0.0;
     }
-    __syncthreads();
+  // Aug is dead until the write-back: its first 2n entries hold the column
+  // copies of even and odd steps (ld > n, so n * ld >= 2n)
+  LDS double* col[2] = {Aug, Aug + n};
+  lds_barrier();
+  if (w == 0) {
+#pragma unroll
+    for (int s = 0; s < RS; ++s)
+      if (l + 64 * s < n) col[0][l + 64 * s] = a[s][0];
   }
-  for (int j = tid(); j < n; j += kWG) dg[j] = 1.0 / Aug[perm[j] * ld + j];
+  unsigned used = 0;   // bit s: row l + 64 s has been a pivot row
+  for (int j = 0; j < n; ++j) {
+    const int b = j & 1;
+    LDS double* cj = col[b];
+    if (w == (j & 3)) {
+      // the owner of column j selects the pivot from its LDS copy
+      int p = j;
+      if (pivot) {
+        unsigned key[RS];
+        unsigned kmax = 0;
+#pragma unroll
+        for (int s = 0; s < RS; ++s) {
+          const int r = l + 64 * s;
+          const double av = r < n ? fabs(cj[r]) : -1.0;
+          key[s] = (!((used >> s) & 1u) && av >= 0.0) ? __float_as_uint((float)av) : 0u;
+          kmax = max(kmax, key[s]);
+        }
+        kmax = wave_max_u32(kmax);
+        p = n;   // no candidate, or all zero: singular
+        if (kmax != 0u) {
+#pragma unroll
+          for (int s = RS - 1; s >= 0; --s) {
+            const unsigned long long m = __ballot(key[s] == kmax);
+            if (m) p = 64 * s + __builtin_ctzll(m);
+          }
+        }
+      }
+      if (l == 0) {
+        const double pv = p < n ? cj[p] : 0.0;
+        const bool bad = p >= n || !(pivot ? fabs(pv) > 0.0 : pv > 0.0) || !isfinite(pv);
+        s_piv[b] = bad ? -1 : p;
+        if (!bad) {
+          const double iv = 1.0 / pv;
+          s_inv[b] = iv;
+          perm[j] = p;
+          dg[j] = iv;
+        }
+      }
+    }
+    lds_barrier();
+    const int p = s_piv[b];
+    if (p < 0) return false;
+    const double inv = s_inv[b];
+    double mult[RS];
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      const int r = l + 64 * s;
+      mult[s] = (r == p || r >= n) ? 0.0 : cj[r] * inv;
+    }
+    if (l == (p & 63)) used |= 1u << (p >> 6);
+    const int pl = p & 63;
+    const bool hi_slot = RS > 1 && p >= 64;
+    LDS double* cn = col[b ^ 1];
+    const int kn = (j + 1 - w) >> 2;   // the next column's slot, if this wave owns it
+    const bool owner_next = ((j + 1) & 3) == w && j + 1 < n;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const double pr = readlane_f64(hi_slot ? a[RS - 1][k] : a[0][k], pl);
+#pragma unroll
+      for (int s = 0; s < RS; ++s) a[s][k] = fma(-mult[s], pr, a[s][k]);
+      if (owner_next && k == kn) {
+#pragma unroll
+        for (int s = 0; s < RS; ++s)
+          if (l + 64 * s < n) cn[l + 64 * s] = a[s][k];
+      }
+    }
+  }
+  lds_barrier();   // last step's reads of the column copy
+  // the right part back to LDS (the left part is dead)
+#pragma unroll
+  for (int s = 0; s < RS; ++s)
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int r = l + 64 * s, c = w + 4 * k;
+      if (r < n && c >= n && c < ld) Aug[r * ld + c] = a[s][k];
+    }
   __syncthreads();
   return true;
+}
+
+// n <= 128 rows, n < ld <= 160 columns.
+__device__ inline bool wg_gj_eliminate(int n, int ld, LDS double* Aug, bool pivot, LDS int* perm, LDS int* used,
+                                       LDS double* dg) {
+  __shared__ int s_piv_[2];
+  __shared__ double s_inv_[2];
+  LDS int* s_piv = (LDS int*)s_piv_;
+  LDS double* s_inv = (LDS double*)s_inv_;
+  (void)used;
+  if (n <= 64) {
+    if (ld <= 32) return gj_eliminate_regs<1, 8>(n, ld, Aug, pivot, perm, dg, s_piv, s_inv);
+    if (ld <= 64) return gj_eliminate_regs<1, 16>(n, ld, Aug, pivot, perm, dg, s_piv, s_inv);
+    if (ld <= 96) return gj_eliminate_regs<1, 24>(n, ld, Aug, pivot, perm, dg, s_piv, s_inv);
+    if (ld <= 128) return gj_eliminate_regs<1, 32>(n, ld, Aug, pivot, perm, dg, s_piv, s_inv);
+    return gj_eliminate_regs<1, 40>(n, ld, Aug, pivot, perm, dg, s_piv, s_inv);
+  }
+  if (ld <= 128) return gj_eliminate_regs<2, 32>(n, ld, Aug, pivot, perm, dg, s_piv, s_inv);
+  return gj_eliminate_regs<2, 40>(n, ld, Aug, pivot, perm, dg, s_piv, s_inv);
 }
 
 // Out[j][c] = scale * (M^{-1} R)[j][c0 + c] for c < m, after wg_gj_eliminate,

@@ -28,6 +28,10 @@ namespace gsls {
 
 __host__ __device__ inline int sls_odd(int x) { return x | 1; }
 
+// Row slots per wave and pass of the block copies (16 loads in flight per
+// thread: rows wave + 4q of the pass, columns lane and lane + 64).
+constexpr int kSlsRowSlots = 8;
+
 struct SlsLayout {
   int ldP, ldW, ldZ, ldAB, ldG, ldY;
   size_t P, W, Z, AB, G, Y, M, T, aug, bytes;
@@ -75,15 +79,34 @@ __global__ void __launch_bounds__(kWG) k_sls(SlsArgs a) {
   const size_t tau_stride = (size_t)N * N * nc + (size_t)N * nf;
   const unsigned total = (unsigned)a.count * N;
 
+  // Block copies global -> LDS in passes of 32 rows, each issuing all of a
+  // thread's loads before its first LDS store (one memory latency per pass).
+  auto load_block = [&](int m, int n, auto src, LDS float* dst, int ldd) {
+    for (int q0 = 0; 4 * q0 < m; q0 += kSlsRowSlots) {
+      float v[kSlsRowSlots][2];
+#pragma unroll
+      for (int q = 0; q < kSlsRowSlots; ++q)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int r = wave() + 4 * (q0 + q), c = lane() + 64 * b;
+          v[q][b] = (r < m && c < n) ? src(r, c) : 0.f;
+        }
+#pragma unroll
+      for (int q = 0; q < kSlsRowSlots; ++q)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int r = wave() + 4 * (q0 + q), c = lane() + 64 * b;
+          if (r < m && c < n) dst[r * ldd + c] = v[q][b];
+        }
+    }
+  };
   auto load_stage = [&](int k) {   // AB <- [A_k | B_k], G <- G_k
     const float* Ak = a.A + (size_t)k * nx * nx;
     const float* Bk = a.B + (size_t)k * nx * nu;
     const float* Gk = a.G + (size_t)k * nc * nxu;
-    for (int r = wave(); r < nx; r += 4)
-      for (int c = lane(); c < nxu; c += 64)
-        AB[r * lay.ldAB + c] = c < nx ? Ak[(size_t)r * nx + c] : Bk[(size_t)r * nu + (c - nx)];
-    for (int r = wave(); r < nc; r += 4)
-      for (int c = lane(); c < nxu; c += 64) G[r * lay.ldG + c] = Gk[(size_t)r * nxu + c];
+    load_block(nx, nxu, [&](int r, int c) { return c < nx ? Ak[(size_t)r * nx + c] : Bk[(size_t)r * nu + (c - nx)]; },
+               AB, lay.ldAB);
+    load_block(nc, nxu, [&](int r, int c) { return Gk[(size_t)r * nxu + c]; }, G, lay.ldG);
   };
 
   while (true) {
@@ -118,13 +141,11 @@ __global__ void __launch_bounds__(kWG) k_sls(SlsArgs a) {
       __syncthreads();
       // W = P [A | B];  Z = [A | B]^T W + blkdiag(Qbar, Rbar)
       wg_mm_f32(nx, nxu, nx, 1.f, P, lay.ldP, false, AB, lay.ldAB, false, 0.f, W, lay.ldW);
-      for (int r = wave(); r < nxu; r += 4)
-        for (int c = lane(); c < nxu; c += 64) {
-          float v = 0.f;
-          if (r < nx && c < nx) v = a.Qb[(size_t)r * nx + c];
-          if (r >= nx && c >= nx) v = a.Rb[(size_t)(r - nx) * nu + (c - nx)];
-          Z[r * lay.ldZ + c] = v;
-        }
+      load_block(nxu, nxu, [&](int r, int c) {
+        if (r < nx && c < nx) return a.Qb[(size_t)r * nx + c];
+        if (r >= nx && c >= nx) return a.Rb[(size_t)(r - nx) * nu + (c - nx)];
+        return 0.f;
+      }, Z, lay.ldZ);
       __syncthreads();
       wg_mm_f32(nxu, nxu, nx, 1.f, AB, lay.ldAB, true, W, lay.ldW, false, 1.f, Z, lay.ldZ);
       // Z += G^T diag(tau) G
@@ -200,8 +221,7 @@ __global__ void __launch_bounds__(kWG) k_sls(SlsArgs a) {
       __syncthreads();
       // Phi^u = K_k Phi^x  (rows nx.. of Y)
       const float* Kk = Kst + (size_t)k * nu * nx;
-      for (int r = wave(); r < nu; r += 4)
-        for (int c = lane(); c < nx; c += 64) Z[r * lay.ldZ + c] = Kk[(size_t)r * nx + c];
+      load_block(nu, nx, [&](int r, int c) { return Kk[(size_t)r * nx + c]; }, Z, lay.ldZ);
       __syncthreads();
       wg_mm_f32(nu, nx, nx, 1.f, Z, lay.ldZ, false, Y, lay.ldY, false, 0.f, Y + nx * lay.ldY, lay.ldY);
       if (a.Phu && inst == 0) {

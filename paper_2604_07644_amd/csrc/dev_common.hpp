@@ -179,24 +179,52 @@ constexpr int kGemmSmem = 2 * 16 * 5 * kKT;   // elements of T needed by wg_gemm
 __device__ __forceinline__ int wave() { return threadIdx.x >> 6; }
 __device__ __forceinline__ int lane() { return threadIdx.x & 63; }
 
-// Copy / convert a matrix block: dst[i*ldd + j] = src[i*lds + j] (or transposed).
-template <typename TD, typename TS>
-__device__ void wg_copy(int m, int n, TD* dst, int ldd, const TS* src, int lds, bool trans = false) {
-  for (int i = wave(); i < m; i += 4)
-    for (int j = lane(); j < n; j += 64)
-      dst[(size_t)i * ldd + j] = TD(trans ? src[(size_t)j * lds + i] : src[(size_t)i * lds + j]);
+// Element loops over an m x n block in passes of 32 rows: wave w and lane l
+// take rows w + 4q (q < 8) and columns l, l + 64 (n <= 128) of the pass, and
+// every load of a thread in a pass is issued before its first store, so a
+// pass costs one memory latency instead of one per row.
+constexpr int kPassRows = 8;
+template <typename TV, typename Load, typename Store>
+__device__ __forceinline__ void wg_block_pass(int m, int n, Load load, Store store) {
+  for (int q0 = 0; 4 * q0 < m; q0 += kPassRows) {
+    TV v[kPassRows][2];
+#pragma unroll
+    for (int q = 0; q < kPassRows; ++q)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int i = wave() + 4 * (q0 + q), j = lane() + 64 * b;
+        if (i < m && j < n) v[q][b] = load(i, j);
+      }
+#pragma unroll
+    for (int q = 0; q < kPassRows; ++q)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int i = wave() + 4 * (q0 + q), j = lane() + 64 * b;
+        if (i < m && j < n) store(i, j, v[q][b]);
+      }
+  }
 }
 
-// Symmetrise a square matrix in place: P = (P + P^T) / 2.
+// Copy / convert a matrix block: dst[i*ldd + j] = src[i*lds + j] (or transposed), n <= 128.
+template <typename TD, typename TS>
+__device__ void wg_copy(int m, int n, TD* dst, int ldd, const TS* src, int lds, bool trans = false) {
+  wg_block_pass<TD>(m, n, [&](int i, int j) { return TD(trans ? src[(size_t)j * lds + i] : src[(size_t)i * lds + j]); },
+                    [&](int i, int j, TD v) { dst[(size_t)i * ldd + j] = v; });
+}
+
+// Symmetrise a square matrix in place: P = (P + P^T) / 2 (n <= 128).  Every
+// thread reads both halves of its pairs before any write; the result is
+// written to both triangles.
 template <typename T>
 __device__ void wg_symmetrize(int n, T* P, int ld) {
   __syncthreads();
-  for (int i = wave(); i < n; i += 4)
-    for (int j = i + 1 + lane(); j < n; j += 64) {
-      T s = T(0.5) * (P[(size_t)i * ld + j] + P[(size_t)j * ld + i]);
-      P[(size_t)i * ld + j] = s;
-      P[(size_t)j * ld + i] = s;
-    }
+  wg_block_pass<T>(n, n, [&](int i, int j) { return j > i ? T(0.5) * (P[(size_t)i * ld + j] + P[(size_t)j * ld + i]) : T(0); },
+                   [&](int i, int j, T v) {
+                     if (j > i) {
+                       P[(size_t)i * ld + j] = v;
+                       P[(size_t)j * ld + i] = v;
+                     }
+                   });
   __syncthreads();
 }
 

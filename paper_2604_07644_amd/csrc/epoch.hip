@@ -42,29 +42,23 @@ __device__ inline LdsPtrs carve(char* base_generic) {
   return p;
 }
 
-// Aug <- [I + X | I] for the n x n matrix X (T, any memory), FP64.
+// Aug <- [shift I + X | I] for the n x n matrix X (T, any memory), FP64; the
+// loads of X are batched (wg_block_pass).
 template <typename T>
-__device__ inline void fill_aug_ipx(int n, LDS double* Aug, const T* X) {
+__device__ inline void fill_aug_shift(int n, LDS double* Aug, const T* X, double shift) {
   const int ld = 2 * n;
+  wg_block_pass<double>(n, n, [&](int i, int c) { return double(X[(size_t)i * n + c]) + (i == c ? shift : 0.0); },
+                        [&](int i, int c, double v) { Aug[i * ld + c] = v; });
   for (int i = wave(); i < n; i += 4)
-    for (int c = lane(); c < ld; c += 64) {
-      double v;
-      if (c < n) v = double(X[(size_t)i * n + c]) + (i == c ? 1.0 : 0.0);
-      else v = (c - n == i) ? 1.0 : 0.0;
-      Aug[i * ld + c] = v;
-    }
+    for (int c = lane(); c < n; c += 64) Aug[i * ld + n + c] = c == i ? 1.0 : 0.0;
   __syncthreads();
 }
-
-// Aug <- [X | I] for the symmetric n x n matrix X (T, ld n), FP64.
+// Aug <- [I + X | I].
 template <typename T>
-__device__ inline void fill_aug(int n, LDS double* Aug, const T* X) {
-  const int ld = 2 * n;
-  for (int i = wave(); i < n; i += 4)
-    for (int c = lane(); c < ld; c += 64)
-      Aug[i * ld + c] = c < n ? double(X[(size_t)i * n + c]) : ((c - n == i) ? 1.0 : 0.0);
-  __syncthreads();
-}
+__device__ inline void fill_aug_ipx(int n, LDS double* Aug, const T* X) { fill_aug_shift(n, Aug, X, 1.0); }
+// Aug <- [X | I] for the symmetric n x n matrix X (T, ld n).
+template <typename T>
+__device__ inline void fill_aug(int n, LDS double* Aug, const T* X) { fill_aug_shift(n, Aug, X, 0.0); }
 
 __device__ inline void flag_fail(int* status) {
   if (tid() == 0) atomicMax(status, 1);

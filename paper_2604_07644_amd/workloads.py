@@ -209,6 +209,16 @@ def sls_batch(count=64, N=64, nx=61, nu=12, nc=40, e_var=0.01, cfg_id=3):
     return probs, E, 0.01
 
 
+def robust_case(N=16, nx=6, nu=2, nc=8, cfg_id=6, instance_id=0, e_var=0.01, wbound=0.05):
+    """Robust MPC case: a polytopic QP as in polytopic_lq (one-sided rows,
+    no terminal rows) with disturbance maps E_t ~ N(0, e_var) and the bound
+    |w|_inf <= wbound."""
+    p = polytopic_lq(N, nx, nu, nc, cfg_id=cfg_id, instance_id=instance_id)
+    rng = _rng(cfg_id, 10 ** 9 + 2 + instance_id)
+    E = _normal(rng, e_var, (N, nx, nx))
+    return p, E, wbound
+
+
 NX_CLASSES = (12, 36, 61, 75)
 NU_CLASSES = (4, 12, 19)
 

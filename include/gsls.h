@@ -206,6 +206,47 @@ int gsls_sls_solve_batch(gsls_qp* h, int32_t count, const double* E, const doubl
 int gsls_sls_tau(gsls_qp* h, const double* lambda, const double* Phi_x, const double* Phi_u,
                  double eps, double* tau);
 
+/* ------------------------------------------------------------ robust MPC ---
+ * The alternation of Sec. III-D on the handle's QP, between
+ *  (A) the nominal trajectory: the QP with its rows tightened by the margins h
+ *      of the current controller, l + h <= G xi <= u - h on the finite sides
+ *      (eq. (nmpc_problem_tightened)), solved by the ADMM of gsls_qp_solve
+ *      from a cold start at rho with tolerance tol (the handle's settings);
+ *  (B) the controller: gsls_sls_solve with the App. B weights tau computed
+ *      from the nominal multipliers and the current responses (eps as in
+ *      gsls_sls_tau).
+ * The first controller uses tau = 0.  One pass is (A) then (B); the loop
+ * stops when the margins move by at most htol * max(1, |h|_inf) or after
+ * max_passes passes, then solves (A) once more with the final margins, so the
+ * returned trajectory (gsls_qp_get) and margins belong together.
+ *  x0 [nx] (host); E, Qbar, Rbar, QbarN, rownorm, wbound as for gsls_sls_solve.
+ *  result (nullable): outcome and counts; hmarg [N][nc], hf [nf] (host,
+ *  nullable): the final margins.
+ * The handle's bounds are restored before return.  Return code: GSLS_OK when
+ * the loop ran (its outcome in result->status), an error code otherwise. */
+enum {
+  GSLS_ROBUST_CONVERGED = 1,      /* margins settled                            */
+  GSLS_ROBUST_PASS_LIMIT = 2,     /* max_passes passes without settling         */
+  GSLS_ROBUST_INFEASIBLE = 4,     /* l + h > u - h on some row                  */
+  GSLS_ROBUST_NOMINAL_FAILED = 5  /* a nominal solve did not converge           */
+};
+typedef struct gsls_robust_result {
+  int32_t status;        /* GSLS_ROBUST_*                                          */
+  int32_t passes;        /* controller updates (B)                                 */
+  int32_t qp_solves;     /* nominal solves (A)                                     */
+  int32_t qp_iterations; /* ADMM iterations over all nominal solves                */
+  int32_t qp_status;     /* gsls_result.status of the last nominal solve (0: none) */
+  int32_t reserved;
+  double h_change;       /* max |h_new - h| of the last pass                      */
+  double ms_nominal;     /* device time of the nominal solves                     */
+  double ms_controller;  /* device time of the tau and SLS steps                  */
+} gsls_robust_result;
+
+int gsls_robust_solve(gsls_qp* h, const double* x0, const double* E, const double* Qbar,
+                      const double* Rbar, const double* QbarN, int32_t rownorm, double wbound,
+                      double eps, double rho, double tol, int32_t max_passes, double htol,
+                      gsls_robust_result* result, double* hmarg, double* hf);
+
 /* ------------------------------------------------------------ batches ---
  * Many independent QPs of uneven shape solved in one persistent launch
  * (captured in a HIP graph and replayed on later calls): each workgroup of

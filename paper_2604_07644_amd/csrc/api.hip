@@ -9,6 +9,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <limits>
 #include <type_traits>
 #include <vector>
 
@@ -128,6 +129,9 @@ struct SolverBase {
                         double* hf, double* ms) = 0;
   virtual int phase_cycles(int enable, double* out, int* chunks) = 0;
   virtual int sls_tau(const double* lam, const double* Phx, const double* Phu, double eps, double* tau) = 0;
+  virtual int robust(const double* x0, const double* E, const double* Qb, const double* Rb, const double* QbN,
+                     int rownorm, double wbound, double eps, double rho, double tol, int max_passes, double htol,
+                     gsls_robust_result* res, double* h, double* hf) = 0;
 };
 
 template <typename T>
@@ -605,6 +609,89 @@ struct Solver : SolverBase {
     if (hipStreamSynchronize(stream) != hipSuccess) return GSLS_ERR_HIP;
     return d2h(tau, sb.taud, (size_t)N * N * nc + (size_t)N * nf);
   }
+
+  // App. B weights from the multipliers lam (host) and the responses that the
+  // last sls_common(want_phi) left in device memory; tau to host.
+  int tau_from_last_phi(const double* lam, double eps, double* tau, float* ms) {
+    const int N = hd.N, nc = hd.nc, nf = hd.nf;
+    if (hipMemcpyAsync(sb.lam, lam, (size_t)hd.m * 8, hipMemcpyHostToDevice, stream) != hipSuccess) return GSLS_ERR_HIP;
+    SlsArgs sa{};
+    sa.N = N; sa.nx = hd.nx; sa.nu = hd.nu; sa.nc = nc; sa.nf = nf; sa.count = 1;
+    sa.G = sb.G; sa.CN = sb.CN; sa.Phx = sb.Phx; sa.Phu = sb.Phu; sa.hj = sb.hj; sa.hfj = sb.hfj;
+    int rc;
+    if (hipEventRecord(ev[0], stream) != hipSuccess) return GSLS_ERR_HIP;
+    if ((rc = launch_sls_beta(sa, stream))) return rc;
+    if ((rc = launch_sls_tau(N, nc, nf, sb.hj, sb.hfj, sb.lam, eps, sb.taud, stream))) return rc;
+    if (hipEventRecord(ev[1], stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (ms) (void)hipEventElapsedTime(ms, ev[0], ev[1]);
+    return d2h(tau, sb.taud, (size_t)N * N * nc + (size_t)N * nf);
+  }
+
+  // The alternation of Sec. III-D (see gsls_robust_solve in gsls.h).
+  int robust(const double* x0, const double* E, const double* Qb, const double* Rb, const double* QbN,
+             int rownorm, double wbound, double eps, double rho, double tol, int max_passes, double htol,
+             gsls_robust_result* res, double* hout, double* hfout) override {
+    const int N = hd.N, nc = hd.nc, nf = hd.nf, m = hd.m;
+    if (!x0 || max_passes < 0 || !(htol >= 0.0) || !(eps > 0.0) || !(rho > 0.0) || !(tol >= 0.0))
+      return GSLS_ERR_INVALID_ARG;
+    const size_t ts = (size_t)N * N * nc + (size_t)N * nf;
+    const std::vector<double> l0 = hd.l, u0 = hd.u;
+    std::vector<double> hrow(m), hnew(m), lt(m), ut(m), lam(m), tau(ts);
+    gsls_robust_result out{};
+    auto read_h = [&](std::vector<double>& dst) -> int {
+      int e = d2h(dst.data(), sb.h, (size_t)N * nc);
+      return e ? e : d2h(dst.data() + (size_t)N * nc, sb.hf, (size_t)nf);
+    };
+    float t = 0.f;
+    int rc = sls_common(1, E, nullptr, Qb, Rb, QbN, rownorm, wbound, true, &t);   // tau = 0
+    if (rc || (rc = read_h(hrow))) return rc;
+    out.ms_controller += t;
+    double change = std::numeric_limits<double>::infinity();
+    int status = GSLS_ROBUST_PASS_LIMIT;
+    while (true) {
+      bool cross = false;
+      for (int i = 0; i < m; ++i) {
+        lt[i] = std::isfinite(l0[i]) ? l0[i] + hrow[i] : l0[i];
+        ut[i] = std::isfinite(u0[i]) ? u0[i] - hrow[i] : u0[i];
+        cross = cross || lt[i] > ut[i];
+      }
+      if (cross) { status = GSLS_ROBUST_INFEASIBLE; break; }
+      if ((rc = update_bounds(lt.data(), ut.data(), 0))) break;
+      gsls_result r{};
+      if ((rc = solve(x0, 0, rho, tol, nullptr, nullptr, 0, &r))) break;
+      ++out.qp_solves;
+      out.qp_iterations += r.iterations;
+      out.qp_status = r.status;
+      out.ms_nominal += r.ms_total;
+      if (r.status != GSLS_SOLVED) { status = GSLS_ROBUST_NOMINAL_FAILED; break; }
+      if (status == GSLS_ROBUST_CONVERGED || out.passes >= max_passes) break;
+      if ((rc = get(nullptr, nullptr, nullptr, lam.data()))) break;
+      if ((rc = tau_from_last_phi(lam.data(), eps, tau.data(), &t))) break;
+      out.ms_controller += t;
+      if ((rc = sls_common(1, E, tau.data(), Qb, Rb, QbN, rownorm, wbound, true, &t))) break;
+      out.ms_controller += t;
+      if ((rc = read_h(hnew))) break;
+      change = 0.0;
+      double hmax = 0.0;
+      for (int i = 0; i < m; ++i) {
+        change = std::max(change, std::fabs(hnew[i] - hrow[i]));
+        hmax = std::max(hmax, std::fabs(hnew[i]));
+      }
+      hrow.swap(hnew);
+      ++out.passes;
+      if (change <= htol * std::max(1.0, hmax)) status = GSLS_ROBUST_CONVERGED;
+    }
+    const int rc_restore = update_bounds(l0.data(), u0.data(), 0);
+    if (rc) return rc;
+    if (rc_restore) return rc_restore;
+    out.status = status;
+    out.h_change = change;
+    if (hout) std::copy(hrow.begin(), hrow.begin() + (size_t)N * nc, hout);
+    if (hfout) std::copy(hrow.begin() + (size_t)N * nc, hrow.end(), hfout);
+    if (res) *res = out;
+    return GSLS_OK;
+  }
 };
 
 }  // namespace gsls
@@ -760,6 +847,14 @@ int gsls_sls_tau(gsls_qp* h, const double* lambda, const double* Phi_x, const do
                  double* tau) {
   if (!h) return GSLS_ERR_INVALID_ARG;
   return h->impl->sls_tau(lambda, Phi_x, Phi_u, eps, tau);
+}
+
+int gsls_robust_solve(gsls_qp* h, const double* x0, const double* E, const double* Qbar, const double* Rbar,
+                      const double* QbarN, int32_t rownorm, double wbound, double eps, double rho, double tol,
+                      int32_t max_passes, double htol, gsls_robust_result* result, double* hmarg, double* hf) {
+  if (!h) return GSLS_ERR_INVALID_ARG;
+  return h->impl->robust(x0, E, Qbar, Rbar, QbarN, rownorm, wbound, eps, rho, tol, max_passes, htol, result,
+                         hmarg, hf);
 }
 
 }  // extern "C"

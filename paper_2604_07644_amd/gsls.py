@@ -25,11 +25,24 @@ _dp = ct.POINTER(ct.c_double)
 _fp = ct.POINTER(ct.c_float)
 
 
+# outcomes of gsls_robust_solve
+ROBUST_CONVERGED, ROBUST_PASS_LIMIT, ROBUST_INFEASIBLE, ROBUST_NOMINAL_FAILED = 1, 2, 4, 5
+
+
 class QPDesc(ct.Structure):
     _fields_ = [("N", ct.c_int32), ("nx", ct.c_int32), ("nu", ct.c_int32), ("nc", ct.c_int32),
                 ("nf", ct.c_int32), ("mem", ct.c_int32),
                 ("A", _dp), ("B", _dp), ("b", _dp), ("Q", _dp), ("R", _dp), ("S", _dp),
                 ("q", _dp), ("r", _dp), ("C", _dp), ("D", _dp), ("CN", _dp), ("l", _dp), ("u", _dp)]
+
+
+class RobustResult(ct.Structure):
+    _fields_ = [("status", ct.c_int32), ("passes", ct.c_int32), ("qp_solves", ct.c_int32),
+                ("qp_iterations", ct.c_int32), ("qp_status", ct.c_int32), ("reserved", ct.c_int32),
+                ("h_change", ct.c_double), ("ms_nominal", ct.c_double), ("ms_controller", ct.c_double)]
+
+    def asdict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class Settings(ct.Structure):
@@ -82,6 +95,9 @@ def _load():
         "gsls_sls_solve_batch": (ct.c_int, [P, ct.c_int32, _dp, _dp, _dp, _dp, _dp, ct.c_int32, ct.c_double,
                                             _dp, _dp, _dp]),
         "gsls_sls_tau": (ct.c_int, [P, _dp, _dp, _dp, ct.c_double, _dp]),
+        "gsls_robust_solve": (ct.c_int, [P, _dp, _dp, _dp, _dp, _dp, ct.c_int32, ct.c_double, ct.c_double,
+                                         ct.c_double, ct.c_double, ct.c_int32, ct.c_double,
+                                         ct.POINTER(RobustResult), _dp, _dp]),
         "gsls_debug_phase_cycles": (ct.c_int, [P, ct.c_int32, _dp, ct.POINTER(ct.c_int32)]),
         "gsls_qp_setup_batch": (ct.c_int, [ct.POINTER(QPDesc), ct.c_int32, ct.POINTER(Settings), P, ct.POINTER(P)]),
         "gsls_qp_solve_batch": (ct.c_int, [P, ct.POINTER(_dp), _dp, ct.c_double, ct.POINTER(_dp), ct.POINTER(_dp),
@@ -250,6 +266,24 @@ class QP:
         if rc != OK:
             raise GslsError(rc, "gsls_sls_tau")
         return tau
+
+    def robust_solve(self, E, Qbar, Rbar, QbarN, rownorm=1, wbound=1.0, eps=1e-8, rho=1.0, tol=1e-6,
+                     max_passes=10, htol=1e-3, x0=None):
+        """FastSLS alternation (gsls_robust_solve).  Returns the outcome and the
+        final margins; the final nominal trajectory is read with get()."""
+        p = self.prob
+        h = np.zeros((p.N, p.nc)); hf = np.zeros(p.nf)
+        x0 = _f64(p.x0 if x0 is None else x0)
+        E = _f64(E); Qbar = _f64(Qbar); Rbar = _f64(Rbar); QbarN = _f64(QbarN)
+        res = RobustResult()
+        rc = lib.gsls_robust_solve(self.h, _ptr(x0), _ptr(E), _ptr(Qbar), _ptr(Rbar), _ptr(QbarN), int(rownorm),
+                                   float(wbound), float(eps), float(rho), float(tol), int(max_passes), float(htol),
+                                   ct.byref(res), _ptr(h), _ptr(hf))
+        if rc != OK:
+            raise GslsError(rc, "gsls_robust_solve")
+        out = res.asdict()
+        out.update(h=h, hf=hf)
+        return out
 
 
 class Batch:

@@ -219,6 +219,38 @@ def robust_case(N=16, nx=6, nu=2, nc=8, cfg_id=6, instance_id=0, e_var=0.01, wbo
     return p, E, wbound
 
 
+def pendulum_like(N=3000, links=15, kappa=1.0, cfg_id=7, instance_id=0, dt=0.02, umax=2.0):
+    """Torque-limited n-link-pendulum-shaped LTV-QP at the paper's long-horizon
+    scale (its pendulum model is not given): nx = 2n (angles and rates),
+    nu = n (joint torques).  A_t = [[I, dt I], [dt K_t, I]] with K_t = (G_t +
+    G_t^T)/2, G_t ~ N(0, 1/n) (the linearisation about the upright position:
+    an indefinite stiffness), B_t = [[0], [dt M^-1]] with the shared mass
+    matrix M = L L^T + I, L ~ N(0, 1/n); torque rows -umax <= u <= umax
+    (C = 0, D = I, nc = n), no terminal rows; Q_t = diag of nx values
+    log-spaced from 1 to kappa (kappa: the cost's condition number), Q_N = Q,
+    R_t = 0.1 I, q = r = 0; x0 ~ N(0, 0.25).  N = 3000, n = 15 gives 135,000
+    decision variables."""
+    nx, nu = 2 * links, links
+    rng = _rng(cfg_id, instance_id)
+    L = _normal(rng, 1.0 / links, (links, links))
+    Minv = np.linalg.inv(L @ L.T + np.eye(links))
+    A = np.empty((N, nx, nx)); B = np.zeros((N, nx, nu))
+    for t in range(N):
+        G = _normal(rng, 1.0 / links, (links, links))
+        K = 0.5 * (G + G.T)
+        A[t] = np.block([[np.eye(links), dt * np.eye(links)], [dt * K, np.eye(links)]])
+        B[t, links:, :] = dt * Minv
+    qd = np.logspace(0.0, np.log10(kappa), nx) if kappa > 1.0 else np.ones(nx)
+    Q = np.broadcast_to(np.diag(qd), (N + 1, nx, nx)).copy()
+    R = np.broadcast_to(0.1 * np.eye(nu), (N, nu, nu)).copy()
+    x0 = _normal(rng, 0.25, nx)
+    C = np.zeros((N, nu, nx)); D = np.broadcast_to(np.eye(nu), (N, nu, nu)).copy()
+    l = -umax * np.ones(N * nu); u = umax * np.ones(N * nu)
+    return QPProblem(N, nx, nu, nu, 0, A, B, np.zeros((N, nx)), Q, R, np.zeros((N, nu, nx)),
+                     np.zeros((N + 1, nx)), np.zeros((N, nu)), C, D, np.zeros((0, nx)), l, u, x0,
+                     meta=dict(kind="pendulum_like", cfg_id=cfg_id, instance_id=instance_id, kappa=kappa))
+
+
 NX_CLASSES = (12, 36, 61, 75)
 NU_CLASSES = (4, 12, 19)
 

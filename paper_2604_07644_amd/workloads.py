@@ -251,6 +251,55 @@ def pendulum_like(N=3000, links=15, kappa=1.0, cfg_id=7, instance_id=0, dt=0.02,
                      meta=dict(kind="pendulum_like", cfg_id=cfg_id, instance_id=instance_id, kappa=kappa))
 
 
+def dubins_scenario(N=60, n_obs=3, seed=0, dt=0.1, v=1.0):
+    """Dubins car (App. C): speed v, time step dt, a straight reference along
+    +x at the car's speed, x_ref_k = (k dt v, 0, 0), u_ref = 0; n_obs circular
+    obstacles with centres x ~ U[0.25, 0.75] of the path length, radii
+    r ~ U[0.25, 0.4] and y = r - U[0.05, 0.15] (all on the left), so the
+    reference (and the straight initial guess) cuts 5-15 cm into each;
+    |omega| <= 1.5; Q = diag(1, 1, 0.1), Q_N = 10 Q,
+    R = 0.1; disturbance scaling E = 0.025 I (App. C).  Returns a dict of model
+    parameters, the initial state and an initial nominal (X, U)."""
+    rng = _rng(8, seed)
+    Lp = N * dt * v
+    cx = np.sort(rng.uniform(0.25 * Lp, 0.75 * Lp, n_obs))
+    r = rng.uniform(0.25, 0.4, n_obs)
+    cy = r - rng.uniform(0.05, 0.15, n_obs)
+    x_ref = np.zeros((N + 1, 3)); x_ref[:, 0] = dt * v * np.arange(N + 1)
+    Q = np.diag([1.0, 1.0, 0.1])
+    return dict(kind=1, N=N, dt=dt, v=v, Q=Q, R=0.1 * np.eye(1), QN=10.0 * Q, x_ref=x_ref,
+                u_ref=np.zeros((N, 1)), u_min=np.array([-1.5]), u_max=np.array([1.5]),
+                obstacles=np.stack([cx, cy, r], axis=1), x0=np.zeros(3), X=x_ref.copy(),
+                U=np.zeros((N, 1)), E=0.025 * np.eye(3))
+
+
+def quadrotor_scenario(N=50, n_obs=2, seed=0, dt=0.05):
+    """Planar quadrotor (App. D: m = 2.0576, g = 9.81, L = 0.25, J = 0.01):
+    a flight from rest at the origin to (2, 0) along a straight reference at
+    constant speed, hover thrust as the input reference, rotor thrusts in
+    [0, 3 m g / 2]; n_obs obstacles with centres x ~ U[0.6, 1.4], radii
+    r ~ U[0.15, 0.25] and |y| = r - U[0.03, 0.08] on alternating sides (the
+    reference cuts into each); Q = diag(5, 5, 1, 0.5, 0.5, 0.1), Q_N = 10 Q,
+    R = 0.1 I; disturbance
+    scaling E = 0.05 diag(0, 0, 0, 1, 1, 0) (App. D).  Returns a dict as
+    dubins_scenario does; the initial nominal is the reference path with
+    hover thrust."""
+    rng = _rng(9, seed)
+    m, g = 2.0576, 9.81
+    hover = m * g / 2.0
+    cx = np.sort(rng.uniform(0.6, 1.4, n_obs))
+    r = rng.uniform(0.15, 0.25, n_obs)
+    cy = (r - rng.uniform(0.03, 0.08, n_obs)) * np.where(np.arange(n_obs) % 2 == 0, 1.0, -1.0)
+    x_ref = np.zeros((N + 1, 6)); x_ref[:, 0] = np.linspace(0.0, 2.0, N + 1)
+    x_ref[:, 3] = 2.0 / (N * dt)
+    Q = np.diag([5.0, 5.0, 1.0, 0.5, 0.5, 0.1])
+    return dict(kind=2, N=N, dt=dt, Q=Q, R=0.1 * np.eye(2), QN=10.0 * Q, x_ref=x_ref,
+                u_ref=np.full((N, 2), hover), u_min=np.zeros(2), u_max=np.full(2, 3.0 * hover),
+                obstacles=np.stack([cx, cy, r], axis=1), x0=np.zeros(6), X=x_ref.copy(),
+                U=np.full((N, 2), hover), E=0.05 * np.diag([0.0, 0.0, 0.0, 1.0, 1.0, 0.0]),
+                mass=m, grav=g, arm=0.25, inertia=0.01)
+
+
 NX_CLASSES = (12, 36, 61, 75)
 NU_CLASSES = (4, 12, 19)
 

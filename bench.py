@@ -218,6 +218,75 @@ def bench_robust(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_sqp(args):
+    """SQP on the Dubins car of App. C at the paper's scale (20 m, 30 obstacles:
+    N=200, dt=0.1, v=1), QP and step tolerance 1e-2 as in the paper's
+    real-time experiments, mixed precision; the config also reports one
+    real-time-iteration update (linearisation, controller synthesis,
+    tightened nominal solve) of the planar quadrotor of App. D (N=40, one
+    obstacle)."""
+    import torch
+    from paper_2604_07644_amd import gsls, workloads as W
+    stream = torch.cuda.current_stream().cuda_stream
+    sc = W.dubins_scenario(N=200, n_obs=30, seed=0)
+    q = gsls.SQP(sc, gsls.default_settings(precision=gsls.MIXED), stream=stream)
+    kw = dict(max_iter=40, alpha=1.0, tol_qp=1e-2, tol_step=1e-2)
+    for _ in range(args.warmup):
+        q.solve(sc["x0"], sc["X"], sc["U"], **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for _ in range(args.steps):
+        res.append(q.solve(sc["x0"], sc["X"], sc["U"], **kw)[2])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    q.close()
+    r = res[-1]
+    ms_qp = float(np.mean([x["ms_qp"] for x in res]))
+    ms_lin = float(np.mean([x["ms_linearize"] for x in res]))
+    # RTI update of the quadrotor
+    sq = W.quadrotor_scenario(N=40, n_obs=1, seed=3)
+    qq = gsls.SQP(sq, gsls.default_settings(precision=gsls.MIXED), stream=stream)
+    I6, I2 = np.eye(6), np.eye(2)
+    rti_kw = dict(rownorm=1, wbound=1.0, tol_qp=1e-2, max_passes=0)
+    qq.rti_step(sq["x0"], sq["X"], sq["U"], sq["E"], I6, I2, I6, **rti_kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rts = [qq.rti_step(sq["x0"], sq["X"], sq["U"], sq["E"], I6, I2, I6, **rti_kw)[2] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    rti_wall = (time.perf_counter() - t1) / args.steps
+    qq.close()
+    nc, N = 30 + 1, 200
+    # floor bytes of one ADMM iteration (as floor_bytes(): nx=3, nu=1, nc=31, nf=30)
+    byts = 4 * (N * (2 * 3 * 3 + 3 * 3 * 1 + 1 + nc * 4) + 30 * 3) * r["qp_iterations"]
+    achieved = byts / (ms_qp * 1e-3) / 1e9
+    line = {
+        "metric": "SQP solves/s (Dubins car, 30 obstacles, N=200, tol 1e-2)",
+        "value": args.steps / wall, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic (seeded scenario; the paper's obstacle layout is not given)",
+        "config": {"workload": "Dubins car (App. C) SQP, N=200, dt=0.1, v=1, 30 obstacles, |omega| <= 1.5",
+                   "status": r["status"], "sqp_iterations": r["iterations"], "qp_iterations": r["qp_iterations"],
+                   "ms_qp": ms_qp, "ms_linearize": ms_lin,
+                   "rti_quadrotor": {"ms_per_update": 1e3 * rti_wall, "status": rts[-1]["status"],
+                                     "qp_iterations": rts[-1]["qp_iterations"],
+                                     "ms_nominal": float(np.mean([x["ms_nominal"] for x in rts])),
+                                     "ms_controller": float(np.mean([x["ms_controller"] for x in rts]))}},
+        "roofline": {"kernel": "k_admm (the SQP's QP solves)", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "floor_bytes_per_solve": byts, "device_ms_per_solve": ms_qp},
+    }
+    if not args.no_cpu:
+        from oracle import sqp as S
+        md = S.from_scenario(sc)
+        t0 = time.perf_counter()
+        S.sqp(md, sc["x0"], sc["X"], sc["U"], **kw)
+        t = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": 1.0 / t, "unit": "solves/s", "cores": 1, "kind": "oracle",
+                                "sample": "one SQP solve of the same scenario (numpy linearisation, FP64 Riccati ADMM)"}
+    print(json.dumps(line), flush=True)
+
+
 def batch_floor_bytes(p):
     """Floor bytes of one cached iteration of a batch instance: as floor_bytes,
     without the constraint matrices when the rows are the plain box [x; u]
@@ -366,6 +435,9 @@ def main():
         return
     if args.workload == "robust":
         bench_robust(args)
+        return
+    if args.workload == "sqp":
+        bench_sqp(args)
         return
 
     import torch

@@ -137,6 +137,13 @@ int gsls_qp_setup(const gsls_qp_desc* desc, const gsls_settings* settings, void*
  * without touching the factorisation: used to tighten rows by SLS margins. */
 int gsls_qp_update_bounds(gsls_qp* h, const double* l, const double* u);
 
+/* Replace all problem data (A, B, b, Q, R, S, q, r, C, D, CN, l, u) of the
+ * handle by those of desc, which must have the handle's dimensions
+ * (GSLS_ERR_DIM otherwise); desc->mem says where desc's arrays live.  The
+ * arrays are copied; the ADMM state is kept.  Used by the SQP iteration of
+ * Sec. III-B, whose QP changes at every linearisation. */
+int gsls_qp_update_data(gsls_qp* h, const gsls_qp_desc* desc);
+
 /* ADMM solve (Sec. III-C / IV-A) from a cold start z = y = 0.
  * x0 [nx] initial state; rho initial penalty (> 0); tol absolute tolerance on
  * both r_p = |G xi - z|_inf and r_d = rho |G^T (z+ - z)|_inf.  Each ADMM
@@ -246,6 +253,75 @@ int gsls_robust_solve(gsls_qp* h, const double* x0, const double* E, const doubl
                       const double* Rbar, const double* QbarN, int32_t rownorm, double wbound,
                       double eps, double rho, double tol, int32_t max_passes, double htol,
                       gsls_robust_result* result, double* hmarg, double* hf);
+
+/* ------------------------------------------------------- analytic models ---
+ * SQP (Sec. III-B, eq. (sqp_qp)) and the real-time iteration (Sec. IV-C) on
+ * the paper's analytic models: the Dubins car of App. C (x = (px, py, theta),
+ * u = omega, speed v) and the planar quadrotor of App. D (x = (px, py, phi,
+ * vx, vy, phidot), u = rotor thrusts; one explicit Euler step of its
+ * continuous dynamics per time step dt).  Rows: per obstacle (cx, cy, r) the
+ * row r^2 - (px-cx)^2 - (py-cy)^2 <= 0 at every stage and at the terminal
+ * state (eq. (obstacle_constraints)), then the input box u_min <= u <= u_max.
+ * Cost: the tracking cost 1/2 |x_k - x_ref_k|_Q^2 + 1/2 |u_k - u_ref_k|_R^2,
+ * terminal 1/2 |x_N - x_ref_N|_QN^2; the QP's Hessian is the cost's (the
+ * iteration's fixed point is the nonlinear problem's KKT point).
+ * Each SQP iteration linearises around the nominal (X, U) on the device (one
+ * thread per stage), solves the QP in (dx, du) from dx_0 = x0 - X_0 and takes
+ * X += alpha dx, U += alpha du. */
+enum { GSLS_MODEL_DUBINS = 1, GSLS_MODEL_QUADROTOR = 2 };
+
+typedef struct gsls_model_desc {
+  int32_t model;             /* GSLS_MODEL_*; nx, nu = 3, 1 or 6, 2            */
+  int32_t N, n_obs;          /* horizon, obstacles (n_obs <= GSLS_MAX_NC - nu) */
+  int32_t reserved;
+  double dt;
+  double v;                  /* Dubins speed                                    */
+  double mass, gravity, arm, inertia;   /* quadrotor m, g, L, J                */
+  const double* obstacles;   /* [n_obs][3]: cx, cy, r                           */
+  const double *u_min, *u_max;          /* [nu]                                */
+  const double *Q, *R, *QN;             /* [nx][nx], [nu][nu], [nx][nx]        */
+  const double *x_ref, *u_ref;          /* [N+1][nx], [N][nu]                  */
+} gsls_model_desc;
+
+typedef struct gsls_sqp_result {
+  int32_t status;        /* 1: step <= tol_step; 2: iteration limit; 5: a QP did not converge */
+  int32_t iterations;    /* SQP iterations                                     */
+  int32_t qp_iterations; /* ADMM iterations over all QPs                       */
+  int32_t qp_status;     /* gsls_result.status of the last QP                  */
+  double step;           /* max |(dx, du)| of the last iteration               */
+  double ms_linearize;   /* device time of the linearisations                  */
+  double ms_qp;          /* device time of the QP solves                       */
+} gsls_sqp_result;
+
+typedef struct gsls_sqp gsls_sqp;
+
+/* Handle for a model with all host-memory parameters; the QP of the first
+ * linearisation (around the nominal X, U: host [N+1][nx], [N][nu]) sets up the
+ * inner QP solver with the given settings.  nx, nu follow from the model. */
+int gsls_sqp_setup(const gsls_model_desc* model, const double* X, const double* U,
+                   const gsls_settings* settings, void* stream, gsls_sqp** out);
+
+/* The linearised QP around (X, U) (host arrays in the gsls_qp_desc layout with
+ * nc = n_obs + nu, nf = n_obs; any output may be NULL). */
+int gsls_sqp_linearize(gsls_sqp* h, const double* X, const double* U, double* A, double* B, double* b,
+                       double* q, double* r, double* C, double* D, double* CN, double* l, double* u);
+
+/* SQP iterations from the nominal (X, U) (host, overwritten with the final
+ * nominal); x0 [nx] the initial state; each QP solved from a cold start at
+ * rho = 1 to tolerance tol_qp. */
+int gsls_sqp_solve(gsls_sqp* h, const double* x0, double* X, double* U, int32_t max_iter, double alpha,
+                   double tol_qp, double tol_step, gsls_sqp_result* result);
+
+/* One real-time-iteration update (Sec. IV-C): one linearisation around (X, U),
+ * the alternation of gsls_robust_solve on that QP (max_passes controller
+ * updates; E is the disturbance scaling, constant over the horizon, [nx][nx]),
+ * and the tightened nominal step X += dx, U += du.  Margins to hmarg [N][nc],
+ * hf [n_obs] (host, nullable). */
+int gsls_rti_step(gsls_sqp* h, const double* x0, double* X, double* U, const double* E,
+                  const double* Qbar, const double* Rbar, const double* QbarN, int32_t rownorm, double wbound,
+                  double tol_qp, int32_t max_passes, gsls_robust_result* result, double* hmarg, double* hf);
+
+void gsls_sqp_free(gsls_sqp* h);
 
 /* ------------------------------------------------------------ batches ---
  * Many independent QPs of uneven shape solved in one persistent launch

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "dev_common.hpp"
+#include "models.hpp"
 #include "solver.hpp"
 
 namespace gsls {
@@ -132,6 +133,7 @@ struct SolverBase {
   virtual int robust(const double* x0, const double* E, const double* Qb, const double* Rb, const double* QbN,
                      int rownorm, double wbound, double eps, double rho, double tol, int max_passes, double htol,
                      gsls_robust_result* res, double* h, double* hf) = 0;
+  virtual int update_data(const HostDesc& h) = 0;
 };
 
 template <typename T>
@@ -407,6 +409,48 @@ struct Solver : SolverBase {
     return GSLS_OK;
   }
 
+  // Replace every stage datum (same dimensions) in place: device copies,
+  // G = [C | D], bounds and the host description; the SLS copies are
+  // refreshed on their next use.
+  int update_data(const HostDesc& h) override {
+    if (h.N != hd.N || h.nx != hd.nx || h.nu != hd.nu || h.nc != hd.nc || h.nf != hd.nf) return GSLS_ERR_DIM;
+    const int N = h.N, nx = h.nx, nu = h.nu, nc = h.nc, nxu = nx + nu;
+    std::vector<std::vector<T>> keep;   // host sources of the asynchronous copies
+    keep.reserve(16);
+    bool ok = true;
+    auto put = [&](T* dst, const std::vector<double>& src) {
+      keep.emplace_back();
+      convert(keep.back(), src);
+      if (!keep.back().empty() &&
+          hipMemcpyAsync(dst, keep.back().data(), keep.back().size() * sizeof(T), hipMemcpyHostToDevice, stream) !=
+              hipSuccess)
+        ok = false;
+    };
+    put(pb.A, h.A); put(pb.B, h.B); put(pb.b, h.b); put(pb.Q, h.Q); put(pb.R, h.R); put(pb.S, h.S);
+    put(pb.q, h.q); put(pb.r, h.r); put(pb.C, h.C); put(pb.D, h.D); put(pb.CN, h.CN);
+    keep.emplace_back((size_t)N * nc * nxu);
+    std::vector<T>& G = keep.back();
+    for (int k = 0; k < N; ++k)
+      for (int r = 0; r < nc; ++r) {
+        for (int j = 0; j < nx; ++j) G[((size_t)k * nc + r) * nxu + j] = T(h.C[((size_t)k * nc + r) * nx + j]);
+        for (int j = 0; j < nu; ++j) G[((size_t)k * nc + r) * nxu + nx + j] = T(h.D[((size_t)k * nc + r) * nu + j]);
+      }
+    if (!G.empty() && hipMemcpyAsync(pb.G, G.data(), G.size() * sizeof(T), hipMemcpyHostToDevice, stream) != hipSuccess)
+      ok = false;
+    if (h.m > 0) {
+      if (hipMemcpyAsync(ld_, h.l.data(), h.m * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess) ok = false;
+      if (hipMemcpyAsync(ud_, h.u.data(), h.m * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess) ok = false;
+    }
+    if (hipStreamSynchronize(stream) != hipSuccess || !ok) return GSLS_ERR_HIP;
+    hd = h;
+    double hn = 0.0;
+    for (double v : h.q) hn = std::max(hn, std::fabs(v));
+    for (double v : h.r) hn = std::max(hn, std::fabs(v));
+    hnorm = hn;
+    sls_dirty = true;
+    return GSLS_OK;
+  }
+
   int update_bounds(const double* l, const double* u, int dev) override {
     if (!l || !u) return GSLS_ERR_INVALID_ARG;
     std::vector<double> lh(hd.m), uh(hd.m);
@@ -450,6 +494,7 @@ struct Solver : SolverBase {
     int* status = nullptr;
   } sb;
   DevArena sls_arena;
+  bool sls_dirty = false;   // stage data replaced since the SLS copies were made
 
   int sls_prepare(int count) {
     const int N = hd.N, nx = hd.nx, nu = hd.nu, nc = hd.nc, nf = hd.nf, nxu = nx + nu;
@@ -464,16 +509,28 @@ struct Solver : SolverBase {
         sls_arena.ok = false;
       return p;
     };
-    if (!sb.ready) {
-      sb.A = upf(cvt(hd.A));
-      sb.B = upf(cvt(hd.B));
+    auto stage_floats = [&]() {
       std::vector<float> G((size_t)N * nc * nxu);
       for (int k = 0; k < N; ++k)
         for (int r = 0; r < nc; ++r) {
           for (int j = 0; j < nx; ++j) G[((size_t)k * nc + r) * nxu + j] = (float)hd.C[((size_t)k * nc + r) * nx + j];
           for (int j = 0; j < nu; ++j) G[((size_t)k * nc + r) * nxu + nx + j] = (float)hd.D[((size_t)k * nc + r) * nu + j];
         }
-      sb.G = upf(G);
+      return G;
+    };
+    if (sb.ready && sls_dirty) {   // same shapes: refresh the copies in place
+      const std::vector<float> A = cvt(hd.A), B = cvt(hd.B), G = stage_floats(), CN = cvt(hd.CN);
+      bool ok = hipMemcpy(sb.A, A.data(), A.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+                hipMemcpy(sb.B, B.data(), B.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+                (G.empty() || hipMemcpy(sb.G, G.data(), G.size() * 4, hipMemcpyHostToDevice) == hipSuccess) &&
+                (CN.empty() || hipMemcpy(sb.CN, CN.data(), CN.size() * 4, hipMemcpyHostToDevice) == hipSuccess);
+      if (!ok) return GSLS_ERR_HIP;
+    }
+    sls_dirty = false;
+    if (!sb.ready) {
+      sb.A = upf(cvt(hd.A));
+      sb.B = upf(cvt(hd.B));
+      sb.G = upf(stage_floats());
       sb.CN = upf(cvt(hd.CN));
       sb.E = sls_arena.alloc<float>((size_t)N * nx * nx);
       sb.Qb = sls_arena.alloc<float>((size_t)nx * nx);
@@ -806,6 +863,16 @@ int gsls_qp_update_bounds(gsls_qp* h, const double* l, const double* u) {
   return h->impl->update_bounds(l, u, h->mem == GSLS_DEVICE);
 }
 
+int gsls_qp_update_data(gsls_qp* h, const gsls_qp_desc* desc) {
+  if (!h) return GSLS_ERR_INVALID_ARG;
+  int rc = gsls::check_dims(desc);
+  if (rc) return rc;
+  gsls::HostDesc hd;
+  if ((rc = gsls::stage_to_host(desc, &hd))) return rc;
+  if ((rc = gsls::validate_host(hd))) return rc;
+  return h->impl->update_data(hd);
+}
+
 int gsls_qp_solve(gsls_qp* h, const double* x0, double rho, double tol, gsls_result* result) {
   if (!h) return GSLS_ERR_INVALID_ARG;
   return h->impl->solve(x0, h->mem == GSLS_DEVICE, rho, tol, nullptr, nullptr, 0, result);
@@ -856,5 +923,212 @@ int gsls_robust_solve(gsls_qp* h, const double* x0, const double* E, const doubl
   return h->impl->robust(x0, E, Qbar, Rbar, QbarN, rownorm, wbound, eps, rho, tol, max_passes, htol, result,
                          hmarg, hf);
 }
+
+}  // extern "C"
+
+// ===================================================== analytic models: SQP
+namespace gsls {
+
+struct SqpState {
+  int N = 0, nx = 0, nu = 0, no = 0, nc = 0, nf = 0, m = 0;
+  hipStream_t stream = nullptr;
+  DevArena arena;
+  ModelDev md{};
+  double *Xd = nullptr, *Ud = nullptr;
+  LinOut lo{};
+  gsls_qp* qp = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  ~SqpState() {
+    if (qp) gsls_qp_free(qp);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  gsls_qp_desc desc(int mem, const HostDesc* h) const {
+    gsls_qp_desc d{};
+    d.N = N; d.nx = nx; d.nu = nu; d.nc = nc; d.nf = nf; d.mem = mem;
+    if (h) {
+      d.A = h->A.data(); d.B = h->B.data(); d.b = h->b.data(); d.Q = h->Q.data(); d.R = h->R.data();
+      d.S = h->S.data(); d.q = h->q.data(); d.r = h->r.data(); d.C = h->C.data(); d.D = h->D.data();
+      d.CN = nf ? h->CN.data() : nullptr; d.l = h->l.data(); d.u = h->u.data();
+    } else {
+      d.A = lo.A; d.B = lo.B; d.b = lo.b; d.Q = lo.Q; d.R = lo.R; d.S = lo.S; d.q = lo.q; d.r = lo.r;
+      d.C = lo.C; d.D = lo.D; d.CN = nf ? lo.CN : nullptr; d.l = lo.l; d.u = lo.u;
+    }
+    return d;
+  }
+  // linearise around the host nominal (X, U); device time to *ms
+  int linearize(const double* X, const double* U, float* ms) {
+    if (hipMemcpyAsync(Xd, X, sizeof(double) * (N + 1) * nx, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(Ud, U, sizeof(double) * N * nu, hipMemcpyHostToDevice, stream) != hipSuccess)
+      return GSLS_ERR_HIP;
+    if (hipEventRecord(ev[0], stream) != hipSuccess) return GSLS_ERR_HIP;
+    int rc = launch_linearize(md, Xd, Ud, lo, stream);
+    if (rc) return rc;
+    if (hipEventRecord(ev[1], stream) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)
+      return GSLS_ERR_HIP;
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, ev[0], ev[1]);
+    if (ms) *ms += t;
+    return GSLS_OK;
+  }
+  int to_host(HostDesc* h) const {
+    gsls_qp_desc d = desc(GSLS_DEVICE, nullptr);
+    return stage_to_host(&d, h);
+  }
+};
+
+static int model_dims(int kind, int* nx, int* nu) {
+  if (kind == GSLS_MODEL_DUBINS) { *nx = 3; *nu = 1; return GSLS_OK; }
+  if (kind == GSLS_MODEL_QUADROTOR) { *nx = 6; *nu = 2; return GSLS_OK; }
+  return GSLS_ERR_INVALID_ARG;
+}
+
+}  // namespace gsls
+
+struct gsls_sqp {
+  gsls::SqpState s;
+};
+
+extern "C" {
+
+int gsls_sqp_setup(const gsls_model_desc* md, const double* X, const double* U, const gsls_settings* settings,
+                   void* stream, gsls_sqp** out) {
+  using namespace gsls;
+  if (!out) return GSLS_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!md || !X || !U) return GSLS_ERR_INVALID_ARG;
+  int nx = 0, nu = 0;
+  int rc = model_dims(md->model, &nx, &nu);
+  if (rc) return rc;
+  if (md->N < 1 || md->N > GSLS_MAX_N || md->n_obs < 0 || md->n_obs + nu > GSLS_MAX_NC) return GSLS_ERR_DIM;
+  if (!(md->dt > 0.0) || !md->u_min || !md->u_max || !md->Q || !md->R || !md->QN || !md->x_ref || !md->u_ref ||
+      (md->n_obs > 0 && !md->obstacles))
+    return GSLS_ERR_INVALID_ARG;
+  if (md->model == GSLS_MODEL_QUADROTOR && (!(md->mass > 0.0) || !(md->inertia > 0.0))) return GSLS_ERR_INVALID_ARG;
+  gsls_sqp* h = new (std::nothrow) gsls_sqp;
+  if (!h) return GSLS_ERR_OOM;
+  SqpState& S = h->s;
+  const int N = md->N, no = md->n_obs;
+  S.N = N; S.nx = nx; S.nu = nu; S.no = no; S.nc = no + nu; S.nf = no; S.m = N * S.nc + no;
+  S.stream = (hipStream_t)stream;
+  auto upd = [&](const double* src, size_t n) -> const double* {
+    double* p = S.arena.alloc<double>(std::max<size_t>(n, 1));
+    if (p && n && hipMemcpy(p, src, n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) S.arena.ok = false;
+    return p;
+  };
+  ModelDev& m = S.md;
+  m.kind = md->model; m.N = N; m.nx = nx; m.nu = nu; m.no = no;
+  m.dt = md->dt; m.v = md->v; m.mass = md->mass; m.grav = md->gravity; m.arm = md->arm; m.inertia = md->inertia;
+  m.obst = upd(md->obstacles, (size_t)no * 3);
+  m.umin = upd(md->u_min, nu); m.umax = upd(md->u_max, nu);
+  m.Q = upd(md->Q, (size_t)nx * nx); m.R = upd(md->R, (size_t)nu * nu); m.QN = upd(md->QN, (size_t)nx * nx);
+  m.xref = upd(md->x_ref, (size_t)(N + 1) * nx); m.uref = upd(md->u_ref, (size_t)N * nu);
+  S.Xd = S.arena.alloc<double>((size_t)(N + 1) * nx);
+  S.Ud = S.arena.alloc<double>((size_t)N * nu);
+  LinOut& o = S.lo;
+  o.A = S.arena.alloc<double>((size_t)N * nx * nx); o.B = S.arena.alloc<double>((size_t)N * nx * nu);
+  o.b = S.arena.alloc<double>((size_t)N * nx); o.Q = S.arena.alloc<double>((size_t)(N + 1) * nx * nx);
+  o.R = S.arena.alloc<double>((size_t)N * nu * nu); o.S = S.arena.alloc<double>((size_t)N * nu * nx);
+  o.q = S.arena.alloc<double>((size_t)(N + 1) * nx); o.r = S.arena.alloc<double>((size_t)N * nu);
+  o.C = S.arena.alloc<double>((size_t)N * S.nc * nx); o.D = S.arena.alloc<double>((size_t)N * S.nc * nu);
+  o.CN = S.arena.alloc<double>((size_t)std::max(no, 1) * nx);
+  o.l = S.arena.alloc<double>((size_t)S.m); o.u = S.arena.alloc<double>((size_t)S.m);
+  if (!S.arena.ok) { delete h; return GSLS_ERR_OOM; }
+  for (auto& e : S.ev)
+    if (hipEventCreate(&e) != hipSuccess) { delete h; return GSLS_ERR_HIP; }
+  HostDesc hd;
+  if ((rc = S.linearize(X, U, nullptr)) || (rc = S.to_host(&hd))) { delete h; return rc; }
+  gsls_qp_desc d = S.desc(GSLS_HOST, &hd);
+  if ((rc = gsls_qp_setup(&d, settings, stream, &S.qp))) { delete h; return rc; }
+  *out = h;
+  return GSLS_OK;
+}
+
+int gsls_sqp_linearize(gsls_sqp* h, const double* X, const double* U, double* A, double* B, double* b, double* q,
+                       double* r, double* C, double* D, double* CN, double* l, double* u) {
+  using namespace gsls;
+  if (!h || !X || !U) return GSLS_ERR_INVALID_ARG;
+  SqpState& S = h->s;
+  int rc = S.linearize(X, U, nullptr);
+  if (rc) return rc;
+  const size_t N = S.N, nx = S.nx, nu = S.nu, nc = S.nc, nf = S.nf;
+  auto d2h = [&](double* dst, const double* src, size_t n) -> int {
+    if (!dst || !n) return GSLS_OK;
+    return hipMemcpy(dst, src, n * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess ? GSLS_OK : GSLS_ERR_HIP;
+  };
+  if ((rc = d2h(A, S.lo.A, N * nx * nx)) || (rc = d2h(B, S.lo.B, N * nx * nu)) || (rc = d2h(b, S.lo.b, N * nx)) ||
+      (rc = d2h(q, S.lo.q, (N + 1) * nx)) || (rc = d2h(r, S.lo.r, N * nu)) || (rc = d2h(C, S.lo.C, N * nc * nx)) ||
+      (rc = d2h(D, S.lo.D, N * nc * nu)) || (rc = d2h(CN, S.lo.CN, nf * nx)) || (rc = d2h(l, S.lo.l, S.m)) ||
+      (rc = d2h(u, S.lo.u, S.m)))
+    return rc;
+  return GSLS_OK;
+}
+
+int gsls_sqp_solve(gsls_sqp* h, const double* x0, double* X, double* U, int32_t max_iter, double alpha,
+                   double tol_qp, double tol_step, gsls_sqp_result* result) {
+  using namespace gsls;
+  if (!h || !x0 || !X || !U || max_iter < 0 || !(alpha > 0.0) || !(alpha <= 1.0) || !(tol_qp >= 0.0) ||
+      !(tol_step >= 0.0))
+    return GSLS_ERR_INVALID_ARG;
+  SqpState& S = h->s;
+  const int N = S.N, nx = S.nx, nu = S.nu;
+  std::vector<double> dX((size_t)(N + 1) * nx), dU((size_t)N * nu), dx0(nx);
+  gsls_sqp_result out{};
+  out.status = 2;
+  float ms_lin = 0.f;
+  int rc = GSLS_OK;
+  for (int it = 0; it < max_iter; ++it) {
+    if ((rc = S.linearize(X, U, &ms_lin))) break;
+    gsls_qp_desc d = S.desc(GSLS_DEVICE, nullptr);
+    if ((rc = gsls_qp_update_data(S.qp, &d))) break;
+    for (int j = 0; j < nx; ++j) dx0[j] = x0[j] - X[j];
+    gsls_result r{};
+    if ((rc = gsls_qp_solve(S.qp, dx0.data(), 1.0, tol_qp, &r))) break;
+    out.qp_iterations += r.iterations;
+    out.qp_status = r.status;
+    out.ms_qp += r.ms_total;
+    if (r.status != GSLS_SOLVED) { out.status = 5; break; }
+    if ((rc = gsls_qp_get(S.qp, dX.data(), dU.data(), nullptr, nullptr))) break;
+    double st = 0.0;
+    for (size_t i = 0; i < dX.size(); ++i) { X[i] += alpha * dX[i]; st = std::max(st, std::fabs(dX[i])); }
+    for (size_t i = 0; i < dU.size(); ++i) { U[i] += alpha * dU[i]; st = std::max(st, std::fabs(dU[i])); }
+    ++out.iterations;
+    out.step = st;
+    if (st <= tol_step) { out.status = 1; break; }
+  }
+  out.ms_linearize = ms_lin;
+  if (rc) return rc;
+  if (result) *result = out;
+  return GSLS_OK;
+}
+
+int gsls_rti_step(gsls_sqp* h, const double* x0, double* X, double* U, const double* E, const double* Qbar,
+                  const double* Rbar, const double* QbarN, int32_t rownorm, double wbound, double tol_qp,
+                  int32_t max_passes, gsls_robust_result* result, double* hmarg, double* hf) {
+  using namespace gsls;
+  if (!h || !x0 || !X || !U || !E) return GSLS_ERR_INVALID_ARG;
+  SqpState& S = h->s;
+  const int N = S.N, nx = S.nx, nu = S.nu;
+  int rc = S.linearize(X, U, nullptr);
+  if (rc) return rc;
+  gsls_qp_desc d = S.desc(GSLS_DEVICE, nullptr);
+  if ((rc = gsls_qp_update_data(S.qp, &d))) return rc;
+  std::vector<double> Es((size_t)N * nx * nx), dx0(nx), dX((size_t)(N + 1) * nx), dU((size_t)N * nu);
+  for (int k = 0; k < N; ++k) std::memcpy(Es.data() + (size_t)k * nx * nx, E, sizeof(double) * nx * nx);
+  for (int j = 0; j < nx; ++j) dx0[j] = x0[j] - X[j];
+  gsls_robust_result rr{};
+  if ((rc = gsls_robust_solve(S.qp, dx0.data(), Es.data(), Qbar, Rbar, QbarN, rownorm, wbound, 1e-8, 1.0, tol_qp,
+                              max_passes, 0.0, &rr, hmarg, hf)))
+    return rc;
+  if (rr.qp_status == GSLS_SOLVED) {
+    if ((rc = gsls_qp_get(S.qp, dX.data(), dU.data(), nullptr, nullptr))) return rc;
+    for (size_t i = 0; i < dX.size(); ++i) X[i] += dX[i];
+    for (size_t i = 0; i < dU.size(); ++i) U[i] += dU[i];
+  }
+  if (result) *result = rr;
+  return GSLS_OK;
+}
+
+void gsls_sqp_free(gsls_sqp* h) { delete h; }
 
 }  // extern "C"

@@ -45,6 +45,22 @@ class RobustResult(ct.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class ModelDesc(ct.Structure):
+    _fields_ = [("model", ct.c_int32), ("N", ct.c_int32), ("n_obs", ct.c_int32), ("reserved", ct.c_int32),
+                ("dt", ct.c_double), ("v", ct.c_double), ("mass", ct.c_double), ("gravity", ct.c_double),
+                ("arm", ct.c_double), ("inertia", ct.c_double), ("obstacles", _dp), ("u_min", _dp),
+                ("u_max", _dp), ("Q", _dp), ("R", _dp), ("QN", _dp), ("x_ref", _dp), ("u_ref", _dp)]
+
+
+class SqpResult(ct.Structure):
+    _fields_ = [("status", ct.c_int32), ("iterations", ct.c_int32), ("qp_iterations", ct.c_int32),
+                ("qp_status", ct.c_int32), ("step", ct.c_double), ("ms_linearize", ct.c_double),
+                ("ms_qp", ct.c_double)]
+
+    def asdict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Settings(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("max_iter", ct.c_int32), ("adaptive_rho", ct.c_int32),
                 ("sigma", ct.c_int32), ("rho_min", ct.c_double), ("rho_max", ct.c_double),
@@ -95,6 +111,14 @@ def _load():
         "gsls_sls_solve_batch": (ct.c_int, [P, ct.c_int32, _dp, _dp, _dp, _dp, _dp, ct.c_int32, ct.c_double,
                                             _dp, _dp, _dp]),
         "gsls_sls_tau": (ct.c_int, [P, _dp, _dp, _dp, ct.c_double, _dp]),
+        "gsls_qp_update_data": (ct.c_int, [P, ct.POINTER(QPDesc)]),
+        "gsls_sqp_setup": (ct.c_int, [ct.POINTER(ModelDesc), _dp, _dp, ct.POINTER(Settings), P, ct.POINTER(P)]),
+        "gsls_sqp_linearize": (ct.c_int, [P, _dp, _dp] + [_dp] * 10),
+        "gsls_sqp_solve": (ct.c_int, [P, _dp, _dp, _dp, ct.c_int32, ct.c_double, ct.c_double, ct.c_double,
+                                      ct.POINTER(SqpResult)]),
+        "gsls_rti_step": (ct.c_int, [P, _dp, _dp, _dp, _dp, _dp, _dp, _dp, ct.c_int32, ct.c_double, ct.c_double,
+                                     ct.c_int32, ct.POINTER(RobustResult), _dp, _dp]),
+        "gsls_sqp_free": (None, [P]),
         "gsls_robust_solve": (ct.c_int, [P, _dp, _dp, _dp, _dp, _dp, ct.c_int32, ct.c_double, ct.c_double,
                                          ct.c_double, ct.c_double, ct.c_int32, ct.c_double,
                                          ct.POINTER(RobustResult), _dp, _dp]),
@@ -284,6 +308,86 @@ class QP:
         out = res.asdict()
         out.update(h=h, hf=hf)
         return out
+
+
+MODEL_DUBINS, MODEL_QUADROTOR = 1, 2
+
+
+class SQP:
+    """SQP and real-time iteration on an analytic model (gsls_sqp_*).  The
+    scenario is a dict as produced by paper_2604_07644_amd.workloads
+    (dubins_scenario / quadrotor_scenario)."""
+
+    def __init__(self, sc, settings: Optional[Settings] = None, stream=None, **kw):
+        self.kind = int(sc["kind"])
+        self.N = int(sc["N"])
+        self.nx, self.nu = (3, 1) if self.kind == MODEL_DUBINS else (6, 2)
+        obst = np.asarray(sc.get("obstacles", np.zeros((0, 3))), dtype=np.float64).reshape(-1, 3)
+        self.n_obs = obst.shape[0]
+        self._keep = [_f64(obst.reshape(-1) if obst.size else np.zeros(3)), _f64(sc["u_min"]), _f64(sc["u_max"]),
+                      _f64(sc["Q"]), _f64(sc["R"]), _f64(sc["QN"]), _f64(sc["x_ref"]), _f64(sc["u_ref"])]
+        d = ModelDesc()
+        d.model, d.N, d.n_obs = self.kind, self.N, self.n_obs
+        d.dt = float(sc["dt"]); d.v = float(sc.get("v", 1.0)); d.mass = float(sc.get("mass", 1.0))
+        d.gravity = float(sc.get("grav", 9.81)); d.arm = float(sc.get("arm", 0.0)); d.inertia = float(sc.get("inertia", 1.0))
+        (d.obstacles, d.u_min, d.u_max, d.Q, d.R, d.QN, d.x_ref, d.u_ref) = [_ptr(a) for a in self._keep]
+        self.desc = d
+        s = settings or default_settings(**kw)
+        X = _f64(sc["X"]); U = _f64(sc["U"])
+        h = ct.c_void_p()
+        rc = lib.gsls_sqp_setup(ct.byref(d), _ptr(X), _ptr(U), ct.byref(s), ct.c_void_p(stream or 0), ct.byref(h))
+        if rc != OK:
+            raise GslsError(rc, "gsls_sqp_setup")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and lib is not None:
+            lib.gsls_sqp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def dims(self):
+        nc = self.n_obs + self.nu
+        return self.N, self.nx, self.nu, nc, self.n_obs
+
+    def linearize(self, X, U):
+        N, nx, nu, nc, nf = self.dims
+        out = dict(A=np.zeros((N, nx, nx)), B=np.zeros((N, nx, nu)), b=np.zeros((N, nx)), q=np.zeros((N + 1, nx)),
+                   r=np.zeros((N, nu)), C=np.zeros((N, nc, nx)), D=np.zeros((N, nc, nu)), CN=np.zeros((nf, nx)),
+                   l=np.zeros(N * nc + nf), u=np.zeros(N * nc + nf))
+        X = _f64(X); U = _f64(U)
+        rc = lib.gsls_sqp_linearize(self.h, _ptr(X), _ptr(U), *[_ptr(out[k]) for k in
+                                                              ("A", "B", "b", "q", "r", "C", "D", "CN", "l", "u")])
+        if rc != OK:
+            raise GslsError(rc, "gsls_sqp_linearize")
+        return out
+
+    def solve(self, x0, X, U, max_iter=20, alpha=1.0, tol_qp=1e-6, tol_step=1e-5):
+        X = np.array(X, dtype=np.float64); U = np.array(U, dtype=np.float64); x0 = _f64(x0)
+        res = SqpResult()
+        rc = lib.gsls_sqp_solve(self.h, _ptr(x0), _ptr(X), _ptr(U), int(max_iter), float(alpha), float(tol_qp),
+                                float(tol_step), ct.byref(res))
+        if rc != OK:
+            raise GslsError(rc, "gsls_sqp_solve")
+        return X, U, res.asdict()
+
+    def rti_step(self, x0, X, U, E, Qbar, Rbar, QbarN, rownorm=1, wbound=1.0, tol_qp=1e-2, max_passes=0):
+        N, nx, nu, nc, nf = self.dims
+        X = np.array(X, dtype=np.float64); U = np.array(U, dtype=np.float64); x0 = _f64(x0)
+        h = np.zeros((N, nc)); hf = np.zeros(nf)
+        E = _f64(E); Qbar = _f64(Qbar); Rbar = _f64(Rbar); QbarN = _f64(QbarN)
+        res = RobustResult()
+        rc = lib.gsls_rti_step(self.h, _ptr(x0), _ptr(X), _ptr(U), _ptr(E), _ptr(Qbar), _ptr(Rbar), _ptr(QbarN),
+                               int(rownorm), float(wbound), float(tol_qp), int(max_passes), ct.byref(res),
+                               _ptr(h), _ptr(hf))
+        if rc != OK:
+            raise GslsError(rc, "gsls_rti_step")
+        out = res.asdict()
+        out.update(h=h, hf=hf)
+        return X, U, out
 
 
 class Batch:

@@ -200,17 +200,14 @@ struct Solver : SolverBase {
   // whether each chunk's operators fit in LDS.
   void choose_chunks(const gsls_settings& s) {
     const int N = hd.N, nx = hd.nx, nu = hd.nu, nc = hd.nc;
-    const size_t budget = 140 * 1024;
-    const size_t sb = sizeof(T) * (size_t)stage_block_elems_host(nx, nu, nc) +
-                      sizeof(T) * (4 * nx + 4 * nu) + sizeof(double) * 6 * nc;
     if (s.chunks_iter > 0) {
       Pi = std::min(s.chunks_iter, N);
     } else {
-      // target stages per chunk: a few for large states, more for small ones
-      int Lt = nx >= 48 ? 4 : (nx >= 24 ? 6 : 8);
-      int Lfit = (int)std::max<size_t>(1, budget / std::max<size_t>(sb, 1));
-      Lt = std::min(Lt, Lfit);
-      Pi = (N + Lt - 1) / Lt;
+      // one stage per workgroup while the horizon fits the co-resident grid:
+      // an iteration's critical path is the chunk-local stage chain (about ten
+      // workgroup barriers per stage) plus a few cross-workgroup hops per
+      // doubling level, and one extra level costs less than one extra stage
+      Pi = N;
     }
     Pi = std::max(1, std::min(Pi, 256));
     Lmax = (N + Pi - 1) / Pi;

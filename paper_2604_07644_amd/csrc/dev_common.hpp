@@ -631,13 +631,36 @@ __device__ __forceinline__ bool ll_get_val<float>(const unsigned long long* p, u
   *v = __uint_as_float(b);
   return ok;
 }
+// Poll cnt <= K words addr(0..cnt) in one round trip per round: every load of a
+// round is issued before any stamp is checked.  Same bounds as ll_get.
+template <int K, typename F>
+__device__ __forceinline__ bool ll_get_batch(F addr, int cnt, uint32_t stamp, uint32_t bits[K], const int* abort) {
+  unsigned n = 0;
+  while (true) {
+    unsigned long long w[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      w[k] = k < cnt ? __hip_atomic_load(addr(k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     : (unsigned long long)stamp << 32;
+    bool all = true;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      all = all && (uint32_t)(w[k] >> 32) == stamp;
+      bits[k] = (uint32_t)w[k];
+    }
+    if (all) return true;
+    if (++n > kSpinLimit) return false;
+    if ((n & 255) == 0 && __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
 template <>
 __device__ __forceinline__ bool ll_get_val<double>(const unsigned long long* p, uint32_t stamp, double* v,
                                                    const int* abort) {
-  uint32_t lo = 0, hi = 0;
-  bool ok = ll_get(p, stamp, &lo, abort);
-  ok = ok && ll_get(p + 1, stamp, &hi, abort);
-  *v = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  uint32_t b[2] = {0, 0};
+  bool ok = ll_get_batch<2>([&](int k) { return p + k; }, 2, stamp, b, abort);
+  *v = __longlong_as_double((long long)(((unsigned long long)b[1] << 32) | b[0]));
   return ok;
 }
 

@@ -50,21 +50,26 @@ namespace gsls {
 
 __device__ __forceinline__ int cbeg(int c, int N, int P) { return (int)(((long long)c * N) / P); }
 
-// WG-wide max reduction (NaN propagates) of kRed per-thread values.
-__device__ inline void wg_max_red(double v[kRed], LDS double* s /* [kWG] */, LDS double* out) {
+// WG-wide max (NaN propagates) of the first nq of kRed per-thread values: a
+// butterfly inside each wave, then one combine of the four wave results.
+// s: LDS [4][kRed]; out[0..nq) is valid after the call.
+__device__ __forceinline__ double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
+__device__ inline void wg_max_red(const double v[kRed], int nq, LDS double* s, LDS double* out) {
+#pragma unroll
   for (int q = 0; q < kRed; ++q) {
-    s[tid()] = v[q];
-    __syncthreads();
-    for (int st = kWG / 2; st > 0; st >>= 1) {
-      if (tid() < st) {
-        double a = s[tid()], b = s[tid() + st];
-        s[tid()] = (b > a || b != b) ? b : a;
-      }
-      __syncthreads();
+    if (q < nq) {
+      double m = v[q];
+      for (int off = 32; off > 0; off >>= 1) m = nanmax(m, __shfl_xor(m, off));
+      if (lane() == 0) s[wave() * kRed + q] = m;
     }
-    if (tid() == 0) out[q] = s[0];
-    __syncthreads();
   }
+  __syncthreads();
+  if (tid() < nq) {
+    double m = s[tid()];
+    for (int w = 1; w < 4; ++w) m = nanmax(m, s[w * kRed + tid()]);
+    out[tid()] = m;
+  }
+  __syncthreads();
 }
 
 template <typename T>
@@ -126,9 +131,9 @@ __host__ __device__ inline AdmmLayout admm_layout(int nx, int nu, int nc, int nf
   // cvec, qv, bv, evv: [Lmax][nx]; hh, kff, rv, fvv: [Lmax][nu]; qN: [nx]
   L.tvec = (size_t)Lmax * (4 * nx + 4 * nu) + nx;
   L.work = 6 * kVec + 2 * kMaxNc + 512;
-  // ys, zs, ls, us, vacc, wprev: [rows]
-  L.dvec = 6 * rows;
-  L.dwork = kWG + 2 * kRed + (size_t)P * kRed;
+  // ys, zs, ls, us, vacc, wprev: [rows]; x accumulator [Lmax+1][nx]; u accumulator [Lmax][nu]
+  L.dvec = 6 * rows + (size_t)(Lmax + 1) * nx + (size_t)Lmax * nu;
+  L.dwork = 4 * kRed + 2 * kRed;
   size_t tbytes = sizeof(T) * (L.ops + L.tvec + L.work);
   tbytes = (tbytes + 15) & ~(size_t)15;
   L.bytes = tbytes + sizeof(double) * (L.dvec + L.dwork);
@@ -206,9 +211,10 @@ __global__ void __launch_bounds__(kWG) k_admm(IterArgs<T> a) {
   LDS double* us = ls + rmax;
   LDS double* vacc = us + rmax;
   LDS double* wprev = vacc + rmax;
-  LDS double* redv = wprev + rmax;                  // [kWG]
-  LDS double* res = redv + kWG;                     // [2*kRed]
-  LDS double* allp = res + 2 * kRed;                // [P*kRed]
+  LDS double* xacc = wprev + rmax;                  // [Lmax+1][nx]  x of the chunk's stages (+ x_N)
+  LDS double* uacc = xacc + (size_t)(Lm + 1) * nx;  // [Lmax][nu]
+  LDS double* redv = uacc + (size_t)Lm * nu;        // [4][kRed]
+  LDS double* res = redv + 4 * kRed;                // [2*kRed]
   __shared__ int s_flag;
   if (tid() == 0) s_flag = 0;
 
@@ -256,6 +262,9 @@ __global__ void __launch_bounds__(kWG) k_admm(IterArgs<T> a) {
     ls[t] = a.l[row0 + t]; us[t] = a.u[row0 + t];
     vacc[t] = 0.0; wprev[t] = 0.0;
   }
+  const int nxs = (L + (last ? 1 : 0)) * nx;       // states owned by this chunk
+  for (int t = tid(); t < nxs; t += kWG) xacc[t] = a.X[(size_t)s * nx + t];
+  for (int t = tid(); t < L * nu; t += kWG) uacc[t] = a.U[(size_t)s * nu + t];
   __syncthreads();
 
   int it = a.ip.it0;
@@ -422,10 +431,10 @@ __global__ void __launch_bounds__(kWG) k_admm(IterArgs<T> a) {
       const int li = i - s;
       const int nr = term ? nf : nc;
       const int lr0 = li * nc;                     // local row offset (terminal rows follow)
-      // X (and U) hold the last iterate: full value or increment added
+      // xacc (and uacc) hold the last iterate: full value or increment added
       for (int j = tid(); j < nx; j += kWG) {
-        const size_t gi = (size_t)i * nx + j;
-        a.X[gi] = full ? (double)xz[j] : a.X[gi] + (double)xz[j];
+        LDS double* xa = xacc + li * nx + j;
+        *xa = full ? (double)xz[j] : *xa + (double)xz[j];
       }
       if (!term) {
         for (int j = tid(); j < nu; j += kWG) xz[nx + j] = kff[li * nu + j];
@@ -434,8 +443,8 @@ __global__ void __launch_bounds__(kWG) k_admm(IterArgs<T> a) {
         for (int j = tid(); j < nu; j += kWG) {
           const T uu = g2[nx + j];
           xz[nx + j] = uu;                                              // xz = [x; u]
-          const size_t gi = (size_t)i * nu + j;
-          a.U[gi] = full ? (double)uu : a.U[gi] + (double)uu;
+          LDS double* ua = uacc + li * nu + j;
+          *ua = full ? (double)uu : *ua + (double)uu;
         }
         __syncthreads();
         wg_gemv_n<T, KR>(nc, nxu, opG(i), ldG, xz, wv, part, false);       // v = C x + D u
@@ -468,9 +477,12 @@ __global__ void __launch_bounds__(kWG) k_admm(IterArgs<T> a) {
       if (nr > 0) {
         if (term) wg_gemv_t<T, KR>(nr, nx, (const T*)pb.CN, nx, wv, tvu, part, false);
         else wg_gemv_t<T, KR>(nr, nxu, opG(i), ldG, wv, tvu, part, false);
-        for (int j = tid(); j < ncol; j += kWG) {
-          double q = rhod * fabs((double)tvu[j]);
-          loc[1] = (q > loc[1] || q != q) ? q : loc[1];
+        for (int j = tid(); j < ncol; j += kWG) loc[1] = nanmax(loc[1], rhod * fabs((double)tvu[j]));
+        if (!sigma_it && !term) {
+          // next state (g2 still holds Abar x + B k); one barrier covers both
+          for (int j = tid(); j < nx; j += kWG) xz[j] = g2[j] + cst * bv[li * nx + j];
+          __syncthreads();
+          continue;
         }
         __syncthreads();
       }
@@ -484,9 +496,9 @@ __global__ void __launch_bounds__(kWG) k_admm(IterArgs<T> a) {
         }
         // |H xi|: Q x + S^T u and S x + R u (only Q_N x_N at the terminal stage),
         // on the accumulated iterate
-        for (int j = tid(); j < nx; j += kWG) tu2[j] = T(a.X[(size_t)i * nx + j]);
+        for (int j = tid(); j < nx; j += kWG) tu2[j] = T(xacc[li * nx + j]);
         if (!term)
-          for (int j = tid(); j < nu; j += kWG) tu[j] = T(a.U[(size_t)i * nu + j]);
+          for (int j = tid(); j < nu; j += kWG) tu[j] = T(uacc[li * nu + j]);
         __syncthreads();
         wg_gemv_n<T, KR>(nx, nx, (const T*)(pb.Q + i * xx), nx, tu2, tvu, part, false);
         if (!term) {
@@ -505,16 +517,29 @@ __global__ void __launch_bounds__(kWG) k_admm(IterArgs<T> a) {
     }
     mark(7);
     // ---------------------------------------------- 8. global reductions
-    wg_max_red(loc, redv, res);
-    for (int q = tid(); q < kRed; q += kWG)
+    const int nq = sigma_it ? kRed : 2;            // the scale terms only feed the rho rule
+    wg_max_red(loc, nq, redv, res);
+    for (int q = tid(); q < nq; q += kWG)
       ll_put_val<double>(a.ll.red + ((size_t)c * kRed + q) * 2, stamp, res[q]);
     {
+      // thread -> (q, workgroups pp = tid / nqp + (kWG / nqp) k); each thread
+      // folds its values, then lanes of equal q combine (q = lane mod nqp)
+      const int nqp = nq == 2 ? 2 : 8, q = tid() % nqp, pstep = kWG / nqp;
+      double m = 0.0;
       bool ok = true;
-      for (int t = tid(); t < P * kRed; t += kWG) {
-        double v;
-        if (!ll_get_val<double>(a.ll.red + (size_t)t * 2, stamp, &v, a.ll.abort)) ok = false;
-        allp[t] = v;
+      if (q < nq) {
+        for (int p0 = tid() / nqp; p0 < P; p0 += 2 * pstep) {
+          const int cnt = p0 + pstep < P ? 4 : 2;      // words: one or two values
+          uint32_t b[4];
+          ok = ok && ll_get_batch<4>(
+                         [&](int k) { return a.ll.red + ((size_t)(p0 + (k >> 1) * pstep) * kRed + q) * 2 + (k & 1); },
+                         cnt, stamp, b, a.ll.abort);
+          m = nanmax(m, __longlong_as_double((long long)(((unsigned long long)b[1] << 32) | b[0])));
+          if (cnt == 4) m = nanmax(m, __longlong_as_double((long long)(((unsigned long long)b[3] << 32) | b[2])));
+        }
       }
+      for (int off = 32; off >= nqp; off >>= 1) m = nanmax(m, __shfl_xor(m, off));
+      if (lane() < nq) redv[wave() * kRed + lane()] = m;
       if (!ok) {
         atomicExch(&s_flag, 1);
         __hip_atomic_store(a.ll.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -522,12 +547,9 @@ __global__ void __launch_bounds__(kWG) k_admm(IterArgs<T> a) {
       __syncthreads();
       if (s_flag) { status = 5; break; }
     }
-    if (tid() < kRed) {
-      double m = 0.0;
-      for (int p = 0; p < P; ++p) {
-        double v = allp[p * kRed + tid()];
-        m = (v > m || v != v) ? v : m;
-      }
+    if (tid() < nq) {
+      double m = redv[tid()];
+      for (int w = 1; w < 4; ++w) m = nanmax(m, redv[w * kRed + tid()]);
       res[kRed + tid()] = m;
     }
     __syncthreads();
@@ -558,10 +580,13 @@ __global__ void __launch_bounds__(kWG) k_admm(IterArgs<T> a) {
     }
   }
   // ----------------------------------------------------- write state back
+  __syncthreads();
   for (int t = tid(); t < rows; t += kWG) {
     a.y[row0 + t] = ys[t];
     a.z[row0 + t] = zs[t];
   }
+  for (int t = tid(); t < nxs; t += kWG) a.X[(size_t)s * nx + t] = xacc[t];
+  for (int t = tid(); t < L * nu; t += kWG) a.U[(size_t)s * nu + t] = uacc[t];
   if (c == 0 && tid() == 0) {
     a.ctl->it = it;
     a.ctl->status = status;

@@ -90,15 +90,6 @@ int launch_epoch(const DevProblem<T>& pb, const DevEpochWork<T>& ew, const DevFa
 template <typename T> size_t admm_lds_bytes(int nx, int nu, int nc, int nf, int Lmax, int P, bool resident);
 template <typename T> int launch_admm(const IterArgs<T>& args, hipStream_t st);
 
-// Elements of one LDS-resident stage block of the iteration kernel (operators
-// F = [[Abar, B], [K, I]], G = [C | D] and Gamma with odd leading dimensions).
-inline int stage_block_elems_host(int nx, int nu, int nc) {
-  auto odd = [](int x) { return x | 1; };
-  const int nxu = nx + nu;
-  int e = nxu * odd(nxu) + nc * odd(nxu) + nu * odd(nu);
-  return (e + 3) & ~3;
-}
-
 struct SlsArgs {
   int N, nx, nu, nc, nf, count;
   const float *A, *B, *G, *CN;     // problem (FP32): [N][nx][nx], [N][nx][nu], [N][nc][nx+nu], [nf][nx]

@@ -214,7 +214,7 @@ struct Solver : SolverBase {
     if (Lmax > 64) { Pi = std::min(256, (N + 63) / 64); Lmax = (N + Pi - 1) / Pi; }
     nlev = ceil_log2(Pi);
     resident = admm_lds_bytes<T>(nx, nu, nc, hd.nf, Lmax, Pi, true) <= 156 * 1024 ? 1 : 0;
-    Pe = s.chunks_epoch > 0 ? s.chunks_epoch : std::min(256, (N + 1) / 2);
+    Pe = s.chunks_epoch > 0 ? s.chunks_epoch : std::min(256, N);   // epoch: one stage per chunk too
     Pe = std::max(1, std::min(std::min(Pe, N), 256));
   }
 

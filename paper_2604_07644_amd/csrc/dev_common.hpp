@@ -43,6 +43,25 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
   return (T*)(((unsigned long long)hi << 32) | lo);
 }
 
+// The same for an LDS pointer, an int and a scalar of 4 or 8 bytes.  Device
+// functions that are not inlined receive their arguments in vector registers;
+// these calls tell the compiler that workgroup-uniform arguments are uniform,
+// so loops over them stay scalar branches and address arithmetic stays scalar.
+template <typename T>
+__device__ __forceinline__ LDS T* uniform_lds(LDS T* p) {
+  return (LDS T*)(uintptr_t)__builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)p);
+}
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform_val(float v) {
+  return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
+}
+__device__ __forceinline__ double uniform_val(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Workgroup barrier that orders LDS only: waits for the thread's own LDS
 // operations, then s_barrier.  Unlike __syncthreads() it does not wait for
 // outstanding global loads and stores, so prefetches stay in flight and
@@ -164,6 +183,11 @@ __device__ void wg_gemm_tt(int m, int n, int k, T alpha, const T* A, int lda, bo
 template <typename T>
 __device__ void wg_gemm(int m, int n, int k, T alpha, const T* A, int lda, bool ta, const T* B,
                         int ldb, bool tb, T beta, T* C, int ldc, LDS T* smem) {
+  m = uniform_int(m); n = uniform_int(n); k = uniform_int(k);
+  lda = uniform_int(lda); ldb = uniform_int(ldb); ldc = uniform_int(ldc);
+  ta = uniform_int(ta) != 0; tb = uniform_int(tb) != 0;
+  alpha = uniform_val(alpha); beta = uniform_val(beta);
+  A = uniform_ptr(A); B = uniform_ptr(B); C = uniform_ptr(C); smem = uniform_lds(smem);
   int mx = max(m, n);
   if (mx <= 16) wg_gemm_tt<T, 1>(m, n, k, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, smem);
   else if (mx <= 32) wg_gemm_tt<T, 2>(m, n, k, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, smem);
@@ -446,6 +470,8 @@ __device__ inline bool wg_gj_eliminate(int n, int ld, LDS double* Aug, bool pivo
   LDS int* s_piv = (LDS int*)s_piv_;
   LDS double* s_inv = (LDS double*)s_inv_;
   (void)used;
+  n = uniform_int(n); ld = uniform_int(ld); pivot = uniform_int(pivot) != 0;
+  Aug = uniform_lds(Aug); perm = uniform_lds(perm); dg = uniform_lds(dg);
   if (n <= 64) {
     if (ld <= 32) return gj_eliminate_regs<1, 8>(n, ld, Aug, pivot, perm, dg, s_piv, s_inv);
     if (ld <= 64) return gj_eliminate_regs<1, 16>(n, ld, Aug, pivot, perm, dg, s_piv, s_inv);

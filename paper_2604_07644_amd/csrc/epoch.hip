@@ -144,26 +144,53 @@ __global__ void __launch_bounds__(kWG) k_elements(DevProblem<T> pb, DevEpochWork
 // (Upsilon = A1^T (I + P2 C1)^{-1} = (M^{-1} A1)^T because P2, C1 are symmetric,
 //  and Psi = A2 M^{-1}.)  S0..S2: n x n global scratch.  Returns false if M is
 // singular.
+// role < 0 computes all three outputs.  Two workgroups can share one combination
+// instead: both invert M (identical arithmetic), role 0 then forms C (Y2, A2 Y2,
+// C) and role 1 forms A and P (P2 A1 first, then Y1, A, P), so neither waits for
+// the other and the critical path is five products and one inverse, not eight.
+// The outputs equal the one-workgroup combination bit for bit.
 template <typename T>
 __device__ bool wg_combine(int n, const T* P1, const T* A1, const T* C1, const T* P2, const T* A2,
-                           const T* C2, T* P, T* A, T* C, T* S0, T* S1, T* S2, const LdsPtrs& L) {
+                           const T* C2, T* P, T* A, T* C, T* S0, T* S1, T* S2, const LdsPtrs& L,
+                           int role = -1) {
   LDS T* gsm = (LDS T*)L.gsm;
+  const bool do_c = role != 1, do_ap = role != 0;
+  if (do_ap && role == 1)
+    wg_gemm<T>(n, n, n, T(1), P2, n, false, A1, n, false, T(0), S2, n, gsm);   // P2 A1 (needs no inverse)
   wg_gemm<T>(n, n, n, T(1), C1, n, false, P2, n, false, T(0), S0, n, gsm);
   fill_aug_ipx(n, L.Aug, S0);
   if (!wg_gj_inverse<T>(n, L.Aug, true, L.perm, L.used, L.dg, S0, n)) return false;
-  wg_gemm<T>(n, n, n, T(1), S0, n, false, A1, n, false, T(0), S1, n, gsm);   // Y1
-  wg_gemm<T>(n, n, n, T(1), S0, n, false, C1, n, false, T(0), S2, n, gsm);   // Y2
-  wg_gemm<T>(n, n, n, T(1), A2, n, false, S1, n, false, T(0), A, n, gsm);
-  wg_gemm<T>(n, n, n, T(1), A2, n, false, S2, n, false, T(0), S0, n, gsm);
-  wg_copy(n, n, C, n, C2, n);
-  __syncthreads();
-  wg_gemm<T>(n, n, n, T(1), S0, n, false, A2, n, true, T(1), C, n, gsm);
-  wg_gemm<T>(n, n, n, T(1), P2, n, false, A1, n, false, T(0), S0, n, gsm);
-  wg_copy(n, n, P, n, P1, n);
-  __syncthreads();
-  wg_gemm<T>(n, n, n, T(1), S1, n, true, S0, n, false, T(1), P, n, gsm);
-  wg_symmetrize(n, P, n);
-  wg_symmetrize(n, C, n);
+  if (role < 0) {
+    wg_gemm<T>(n, n, n, T(1), S0, n, false, A1, n, false, T(0), S1, n, gsm);   // Y1
+    wg_gemm<T>(n, n, n, T(1), S0, n, false, C1, n, false, T(0), S2, n, gsm);   // Y2
+    wg_gemm<T>(n, n, n, T(1), A2, n, false, S1, n, false, T(0), A, n, gsm);
+    wg_gemm<T>(n, n, n, T(1), A2, n, false, S2, n, false, T(0), S0, n, gsm);
+    wg_copy(n, n, C, n, C2, n);
+    __syncthreads();
+    wg_gemm<T>(n, n, n, T(1), S0, n, false, A2, n, true, T(1), C, n, gsm);
+    wg_gemm<T>(n, n, n, T(1), P2, n, false, A1, n, false, T(0), S0, n, gsm);
+    wg_copy(n, n, P, n, P1, n);
+    __syncthreads();
+    wg_gemm<T>(n, n, n, T(1), S1, n, true, S0, n, false, T(1), P, n, gsm);
+    wg_symmetrize(n, P, n);
+    wg_symmetrize(n, C, n);
+    return true;
+  }
+  if (do_c) {
+    wg_gemm<T>(n, n, n, T(1), S0, n, false, C1, n, false, T(0), S2, n, gsm);   // Y2
+    wg_gemm<T>(n, n, n, T(1), A2, n, false, S2, n, false, T(0), S0, n, gsm);   // A2 Y2
+    wg_copy(n, n, C, n, C2, n);
+    __syncthreads();
+    wg_gemm<T>(n, n, n, T(1), S0, n, false, A2, n, true, T(1), C, n, gsm);
+    wg_symmetrize(n, C, n);
+  } else {
+    wg_gemm<T>(n, n, n, T(1), S0, n, false, A1, n, false, T(0), S1, n, gsm);   // Y1
+    wg_gemm<T>(n, n, n, T(1), A2, n, false, S1, n, false, T(0), A, n, gsm);
+    wg_copy(n, n, P, n, P1, n);
+    __syncthreads();
+    wg_gemm<T>(n, n, n, T(1), S1, n, true, S2, n, false, T(1), P, n, gsm);   // + Y1^T (P2 A1)
+    wg_symmetrize(n, P, n);
+  }
   return true;
 }
 
@@ -200,27 +227,33 @@ __global__ void __launch_bounds__(kWG) k_fold(DevProblem<T> pb, DevEpochWork<T> 
 // ---------------------------------------------------- cross-chunk suffix
 // Suffix products of the chunk elements by recursive doubling, one launch per
 // level: S_c <- S_c (x) S_{c + 2^d} (or unchanged when c + 2^d >= Pe).  After
-// ceil(log2 Pe) levels S_c = E_c (x) E_{c+1} (x) ... (x) E_{Pe-1}.
+// ceil(log2 Pe) levels S_c = E_c (x) E_{c+1} (x) ... (x) E_{Pe-1}.  With
+// split, two workgroups share each chunk's combination (blockIdx.x = 2c + role,
+// each with its own half of the chunk's scratch slots).
 template <typename T>
-__global__ void __launch_bounds__(kWG) k_suffix_level(DevProblem<T> pb, DevEpochWork<T> ew, int Pe, int d) {
+__global__ void __launch_bounds__(kWG) k_suffix_level(DevProblem<T> pb, DevEpochWork<T> ew, int Pe, int d,
+                                                      int split) {
   extern __shared__ __align__(16) char lds[];
   LdsPtrs L = carve<T>(lds);
-  const int c = blockIdx.x, nx = pb.nx;
+  const int c = split ? (int)blockIdx.x >> 1 : (int)blockIdx.x, nx = pb.nx;
+  const int role = split ? (int)(blockIdx.x & 1) : -1;
   const size_t xx = (size_t)nx * nx;
   const bool even = (d % 2) == 0;
   const T* sP = even ? ew.fP : ew.gP; const T* sA = even ? ew.fA : ew.gA; const T* sC = even ? ew.fC : ew.gC;
   T* dP = even ? ew.gP : ew.fP; T* dA = even ? ew.gA : ew.fA; T* dC = even ? ew.gC : ew.fC;
   const int h = 1 << d;
   if (c + h < Pe) {
-    T* sc = ew.scratch + (size_t)c * 8 * ew.slot;
+    T* sc = ew.scratch + (size_t)c * 8 * ew.slot + (role == 1 ? 4 * ew.slot : 0);
     if (!wg_combine<T>(nx, sP + c * xx, sA + c * xx, sC + c * xx, sP + (c + h) * xx, sA + (c + h) * xx,
                        sC + (c + h) * xx, dP + c * xx, dA + c * xx, dC + c * xx, sc, sc + ew.slot,
-                       sc + 2 * ew.slot, L))
+                       sc + 2 * ew.slot, L, role))
       flag_fail(ew.status);
   } else {
-    wg_copy(nx, nx, dP + c * xx, nx, sP + c * xx, nx);
-    wg_copy(nx, nx, dA + c * xx, nx, sA + c * xx, nx);
-    wg_copy(nx, nx, dC + c * xx, nx, sC + c * xx, nx);
+    if (role != 1) wg_copy(nx, nx, dC + c * xx, nx, sC + c * xx, nx);
+    if (role != 0) {
+      wg_copy(nx, nx, dP + c * xx, nx, sP + c * xx, nx);
+      wg_copy(nx, nx, dA + c * xx, nx, sA + c * xx, nx);
+    }
   }
 }
 
@@ -393,6 +426,8 @@ int epoch_set_attributes() {
 
 // Enqueue one factor epoch on `st`.  Pe: chunks of the factor scan, Pi: chunks
 // (workgroups) of the iteration kernel, nlev = ceil(log2 Pi).
+constexpr int kEpochSplitMaxWG = 256;   // compute units of the device
+
 template <typename T>
 int launch_epoch(const DevProblem<T>& pb, const DevEpochWork<T>& ew, const DevFactor<T>& fc,
                  double rho, int Pe, int Pi, int nlev, hipStream_t st) {
@@ -403,8 +438,10 @@ int launch_epoch(const DevProblem<T>& pb, const DevEpochWork<T>& ew, const DevFa
   GSLS_LAUNCH_CHECK();
   int nle = 0;
   while ((1 << nle) < Pe) ++nle;
+  // two workgroups per combination while that still fits one per compute unit
+  const int split = 2 * Pe <= kEpochSplitMaxWG ? 1 : 0;
   for (int d = 0; d < nle; ++d) {
-    k_suffix_level<T><<<Pe, kWG, sh, st>>>(pb, ew, Pe, d);
+    k_suffix_level<T><<<split ? 2 * Pe : Pe, kWG, sh, st>>>(pb, ew, Pe, d, split);
     GSLS_LAUNCH_CHECK();
   }
   k_pend<T><<<Pe, kWG, sh, st>>>(pb, ew, Pe, nle % 2);

@@ -355,6 +355,7 @@ __global__ void __launch_bounds__(kWG) k_fixup(DevProblem<T> pb, DevEpochWork<T>
     // ev = Abar^T P b, fv = B^T P b
     wg_gemm<T>(nx, 1, nx, T(1), F, nxu, true, Pb, 1, false, T(0), fc.ev + (size_t)i * nx, 1, gsm);
     wg_gemm<T>(nu, 1, nx, T(1), B, nu, true, Pb, 1, false, T(0), fc.fv + (size_t)i * nu, 1, gsm);
+    if (i == s) break;   // the chunk's first stage: its P is not needed
     // P_i = Q_hat + A^T P A + G^T K
     wg_copy(nx, nx, Pn, nx, ew.Qh + i * xx, nx);
     __syncthreads();

@@ -612,6 +612,7 @@ int launch_admm(const IterArgs<T>& args, hipStream_t st) {
   if (dim <= 32) fn = args.resident ? (const void*)k_admm<T, true, 8> : (const void*)k_admm<T, false, 8>;
   else if (dim <= 64) fn = args.resident ? (const void*)k_admm<T, true, 16> : (const void*)k_admm<T, false, 16>;
   else if (dim <= 80) fn = args.resident ? (const void*)k_admm<T, true, 20> : (const void*)k_admm<T, false, 20>;
+  else if (dim <= 96) fn = args.resident ? (const void*)k_admm<T, true, 24> : (const void*)k_admm<T, false, 24>;
   else fn = args.resident ? (const void*)k_admm<T, true, 28> : (const void*)k_admm<T, false, 28>;
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess)
     return GSLS_ERR_HIP;

@@ -107,6 +107,28 @@ def test_quadruped_fp64_follows_oracle():
     _close_all(g, o, 1e-9)
 
 
+@pytest.mark.parametrize("ci", [0, 4])
+def test_humanoid_shape_fp64_follows_oracle(ci):
+    """nx=75, nu=19 (nx + nu = 94), 40 rows, N=48: the widest iteration
+    variant; ci=4 gives 12-stage chunks whose operators are read from global
+    memory instead of LDS."""
+    p = W.humanoid_qp(1, N=48)
+    r, g = _gpu(p, gsls.FP64, tol=1e-5, ci=ci)
+    o = _orc(p, tol=1e-5)
+    assert r["status"] == gsls.SOLVED and o["status"] == 1
+    assert r["iterations"] == o["iters"] and r["rho_updates"] == o["rho_updates"]
+    _close_all(g, o, 1e-9)
+
+
+def test_humanoid_shape_mixed_parity():
+    p = W.humanoid_qp(0, N=48)
+    r, g = _gpu(p, gsls.MIXED, tol=1e-5)
+    ref = _orc(p, tol=1e-10)
+    assert r["status"] == gsls.SOLVED, r
+    assert _err(g["X"], ref["X"]) <= 1e-4, _err(g["X"], ref["X"])
+    assert _err(g["U"], ref["U"]) <= 1e-4
+
+
 def test_single_stage_and_unconstrained():
     p = W.random_small(1, 3, 2, 2, 1, seed=4)
     r, g = _gpu(p, gsls.FP64, iters=9, adaptive=False)

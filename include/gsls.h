@@ -93,8 +93,10 @@ typedef struct gsls_settings {
   double rho_min;        /* clamp                                          [1e-6] */
   double rho_max;        /*                                                [1e6]  */
   double rho_tol;        /* change rho only if it moves by more than this   [5.0] */
-  int32_t chunks_epoch;  /* horizon chunks for the factor scan (0 = auto)     [0] */
-  int32_t chunks_iter;   /* horizon chunks for the iteration scans (0 = auto) [0] */
+  int32_t chunks_epoch;  /* horizon chunks for the factor scan (0 = auto:     [0]
+                            one stage per chunk, at most 256 chunks) */
+  int32_t chunks_iter;   /* horizon chunks (workgroups) for the iteration      [0]
+                            scans (0 = auto: one stage per workgroup, at most 256) */
 } gsls_settings;
 
 /* Outcome of one solve. */

@@ -129,6 +129,18 @@ def test_humanoid_shape_mixed_parity():
     assert _err(g["U"], ref["U"]) <= 1e-4
 
 
+@pytest.mark.parametrize("N,want", [(1, (1, 1, 1, 1)), (23, (23, 23, 1, 1)), (128, (128, 128, 1, 1)),
+                                     (300, (256, 256, 1, 2))])
+def test_default_layout_is_one_stage_per_workgroup(N, want):
+    """The default scans use one horizon stage per workgroup (factor chunks and
+    iteration workgroups) up to 256, then ceil(N / 256) stages each."""
+    p = W.random_small(N, 5, 3, 4, 3, seed=7)
+    q = gsls.QP(p, gsls.default_settings(precision=gsls.MIXED))
+    _, lay = q.phase_cycles(-1)
+    q.close()
+    assert lay == want, lay
+
+
 def test_single_stage_and_unconstrained():
     p = W.random_small(1, 3, 2, 2, 1, seed=4)
     r, g = _gpu(p, gsls.FP64, iters=9, adaptive=False)

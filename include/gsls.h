@@ -66,7 +66,8 @@ enum {
 #define GSLS_MAX_NX 80
 #define GSLS_MAX_NU 32
 #define GSLS_MAX_NC 64
-#define GSLS_MAX_N 65536
+#define GSLS_MAX_N 65536   /* the single-instance solver (gsls_qp_create) takes N <= 16384:
+                              256 workgroups of at most 64 stages; GSLS_ERR_DIM beyond */
 
 /* One LTV-QP.  Pointer shapes (row-major):
  *   A [N][nx][nx]  B [N][nx][nu]  b [N][nx] (NULL => 0)

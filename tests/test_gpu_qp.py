@@ -141,6 +141,20 @@ def test_default_layout_is_one_stage_per_workgroup(N, want):
     assert lay == want, lay
 
 
+def test_horizon_beyond_the_grid_is_rejected():
+    """256 workgroups of at most 64 stages: N = 16385 is refused with
+    GSLS_ERR_DIM at creation, N = 16384 is accepted."""
+    ok = W.random_small(16384, 2, 1, 0, 0, seed=8)
+    q = gsls.QP(ok, gsls.default_settings(precision=gsls.MIXED))
+    _, lay = q.phase_cycles(-1)
+    q.close()
+    assert lay[1] == 256 and lay[3] == 64
+    bad = W.random_small(16385, 2, 1, 0, 0, seed=8)
+    with pytest.raises(gsls.GslsError) as e:
+        gsls.QP(bad, gsls.default_settings(precision=gsls.MIXED))
+    assert e.value.code == gsls.ERR_DIM
+
+
 def test_single_stage_and_unconstrained():
     p = W.random_small(1, 3, 2, 2, 1, seed=4)
     r, g = _gpu(p, gsls.FP64, iters=9, adaptive=False)

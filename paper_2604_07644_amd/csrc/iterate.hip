@@ -168,6 +168,9 @@ __global__ void __launch_bounds__(kWG) k_admm(IterArgs<T> a) {
   const double rhod = a.ip.rho;
   const int sbe = stage_block_elems(nx, nu, nc);
   constexpr bool kIncremental = sizeof(T) < sizeof(double);
+  // transfer-map loads issued before the partner wait: KR registers per thread,
+  // kept to the narrower variants (the wider ones spill less without them)
+  constexpr bool kPrefetchMaps = KR <= 20;
   unsigned long long* prof = (a.prof && c == 0) ? a.prof : nullptr;
   unsigned long long t_last = 0;
   auto mark = [&](int ph) {
@@ -336,7 +339,7 @@ __global__ void __launch_bounds__(kWG) k_admm(IterArgs<T> a) {
       const int pc = c + (1 << d);
       if (pc < P) {
         const T* Phi = fc.Phi + ((size_t)d * P + c) * xx;
-        if (nx <= 64) {
+        if (kPrefetchMaps && nx <= 64) {
           // issue the transfer-map loads, then wait for the partner's vector
           T pv[KR];
           wg_gemv_sq_pre<T, KR, true>(nx, Phi, nx, pv);
@@ -395,7 +398,7 @@ __global__ void __launch_bounds__(kWG) k_admm(IterArgs<T> a) {
       if (pc >= 0) {
         // g += Phi[d][c - 2^d + 1] g2; the map's loads are issued before the wait
         const T* Phi = fc.Phi + ((size_t)d * P + (c - (1 << d) + 1)) * xx;
-        if (nx <= 64) {
+        if (kPrefetchMaps && nx <= 64) {
           T pv[KR];
           wg_gemv_sq_pre<T, KR, false>(nx, Phi, nx, pv);
           if (!fetch_vec<T>(a.ll.fwd + ((size_t)d * P + pc) * vstride, stamp, g2, nx, a.ll.abort, &s_flag)) {

@@ -37,8 +37,8 @@ METRIC = "QP solves/s and ms/solve at 1e-5 residual; warm-start vs cold-start AD
 # FETCH_SIZE and WRITE_SIZE runs scaled by the same counters on a 256 MiB
 # device copy (profiles/quadruped_k_admm_hbm_traffic.md).  Valid only for the
 # kernel source it was taken on: reported while the hash of that source matches.
-K_ADMM_TRAFFIC = {"src_sha256_16": "8e12a6a449aeb81e", "sources": ("iterate.hip", "dev_common.hpp", "solver.hpp"),
-                  "bytes_per_launch": 259422989.6}
+K_ADMM_TRAFFIC = {"src_sha256_16": "1958d4f523f0555c", "sources": ("iterate.hip", "dev_common.hpp", "solver.hpp"),
+                  "bytes_per_launch": 192072592.3}
 
 
 def kernel_traffic(entry):

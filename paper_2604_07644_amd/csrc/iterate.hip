@@ -590,14 +590,17 @@ __global__ void __launch_bounds__(kWG) k_admm(IterArgs<T> a) {
   }
   for (int t = tid(); t < nxs; t += kWG) a.X[(size_t)s * nx + t] = xacc[t];
   for (int t = tid(); t < L * nu; t += kWG) a.U[(size_t)s * nu + t] = uacc[t];
+  // status is merged with atomicMax by every writer (the host zeroes it before
+  // the launch): a timeout (5) seen by any workgroup outranks the uniform
+  // decision (1-4) that workgroup 0 reports, whatever the order of the writes
   if (c == 0 && tid() == 0) {
     a.ctl->it = it;
-    a.ctl->status = status;
     a.ctl->r_p = fin_rp;
     a.ctl->r_d = fin_rd;
     a.ctl->rho_new = rho_new;
+    atomicMax(&a.ctl->status, status);
   }
-  if (status == 5 && tid() == 0) atomicMax(&a.ctl->status, 5);
+  if (c != 0 && status == 5 && tid() == 0) atomicMax(&a.ctl->status, 5);
 }
 
 template <typename T>

@@ -179,6 +179,13 @@ def _f64(a, shape=None):
     return a
 
 
+def _check_len(a, n, what):
+    """The C side reads exactly n doubles from a: refuse any other length."""
+    if a is not None and a.size != n:
+        raise ValueError(f"{what}: expected {n} values, got {a.size}")
+    return a
+
+
 def make_desc(prob):
     """QPDesc with host pointers for a workloads.QPProblem; returns (desc, keepalive)."""
     N, nx, nu, nc, nf = prob.N, prob.nx, prob.nu, prob.nc, prob.nf
@@ -227,12 +234,15 @@ class QP:
             raise GslsError(rc, "gsls_qp_update_bounds")
 
     def solve(self, x0=None, rho=1.0, tol=1e-5, z0=None, y0=None) -> dict:
-        x0 = _f64(self.prob.x0 if x0 is None else x0)
+        p = self.prob
+        x0 = _check_len(_f64(p.x0 if x0 is None else x0), p.nx, "x0")
         res = Result()
+        if (z0 is None) != (y0 is None):
+            raise ValueError("z0 and y0 go together")
         if z0 is None:
             rc = lib.gsls_qp_solve(self.h, _ptr(x0), rho, tol, ct.byref(res))
         else:
-            z0 = _f64(z0); y0 = _f64(y0)
+            z0 = _check_len(_f64(z0), p.m, "z0"); y0 = _check_len(_f64(y0), p.m, "y0")
             rc = lib.gsls_qp_solve_warm(self.h, _ptr(x0), rho, tol, _ptr(z0), _ptr(y0), ct.byref(res))
         if rc != OK:
             raise GslsError(rc, "gsls_qp_solve")
@@ -297,7 +307,7 @@ class QP:
         final margins; the final nominal trajectory is read with get()."""
         p = self.prob
         h = np.zeros((p.N, p.nc)); hf = np.zeros(p.nf)
-        x0 = _f64(p.x0 if x0 is None else x0)
+        x0 = _check_len(_f64(p.x0 if x0 is None else x0), p.nx, "x0")
         E = _f64(E); Qbar = _f64(Qbar); Rbar = _f64(Rbar); QbarN = _f64(QbarN)
         res = RobustResult()
         rc = lib.gsls_robust_solve(self.h, _ptr(x0), _ptr(E), _ptr(Qbar), _ptr(Rbar), _ptr(QbarN), int(rownorm),
@@ -348,6 +358,11 @@ class SQP:
     def __del__(self):
         self.close()
 
+    def _check_traj(self, X, U, x0):
+        X = np.array(X, dtype=np.float64); U = np.array(U, dtype=np.float64)
+        _check_len(X, (self.N + 1) * self.nx, "X"); _check_len(U, self.N * self.nu, "U")
+        return X, U, _check_len(_f64(x0), self.nx, "x0")
+
     @property
     def dims(self):
         nc = self.n_obs + self.nu
@@ -366,7 +381,7 @@ class SQP:
         return out
 
     def solve(self, x0, X, U, max_iter=20, alpha=1.0, tol_qp=1e-6, tol_step=1e-5):
-        X = np.array(X, dtype=np.float64); U = np.array(U, dtype=np.float64); x0 = _f64(x0)
+        X, U, x0 = self._check_traj(X, U, x0)
         res = SqpResult()
         rc = lib.gsls_sqp_solve(self.h, _ptr(x0), _ptr(X), _ptr(U), int(max_iter), float(alpha), float(tol_qp),
                                 float(tol_step), ct.byref(res))
@@ -376,7 +391,7 @@ class SQP:
 
     def rti_step(self, x0, X, U, E, Qbar, Rbar, QbarN, rownorm=1, wbound=1.0, tol_qp=1e-2, max_passes=0):
         N, nx, nu, nc, nf = self.dims
-        X = np.array(X, dtype=np.float64); U = np.array(U, dtype=np.float64); x0 = _f64(x0)
+        X, U, x0 = self._check_traj(X, U, x0)
         h = np.zeros((N, nc)); hf = np.zeros(nf)
         E = _f64(E); Qbar = _f64(Qbar); Rbar = _f64(Rbar); QbarN = _f64(QbarN)
         res = RobustResult()
@@ -421,14 +436,22 @@ class Batch:
 
     def solve(self, x0s=None, rhos=1.0, tol=1e-5, z0s=None, y0s=None):
         n = len(self.probs)
-        x0s = [_f64(p.x0) for p in self.probs] if x0s is None else [_f64(x) for x in x0s]
+        x0s = self._x0_list(x0s)
         rh = _f64(np.broadcast_to(np.asarray(rhos, dtype=np.float64), (n,)).copy())
         xp = (_dp * n)(*[_ptr(x) for x in x0s])
         zp = yp = None
         keep = [x0s]
+        if (z0s is None) != (y0s is None):
+            raise ValueError("z0s and y0s go together")
         if z0s is not None:
-            z0s = [None if z is None else _f64(z) for z in z0s]
-            y0s = [None if y is None else _f64(y) for y in y0s]
+            if len(z0s) != n or len(y0s) != n:
+                raise ValueError(f"z0s, y0s: expected {n} entries")
+            z0s = [None if z is None else _check_len(_f64(z), p.m, f"z0s[{i}]")
+                   for i, (z, p) in enumerate(zip(z0s, self.probs))]
+            y0s = [None if y is None else _check_len(_f64(y), p.m, f"y0s[{i}]")
+                   for i, (y, p) in enumerate(zip(y0s, self.probs))]
+            if any((z is None) != (y is None) for z, y in zip(z0s, y0s)):
+                raise ValueError("z0s[i] and y0s[i] go together")
             keep += [z0s, y0s]
             zp = (_dp * n)(*[_ptr(z) for z in z0s])
             yp = (_dp * n)(*[_ptr(y) for y in y0s])
@@ -448,9 +471,17 @@ class Batch:
             raise GslsError(rc, "gsls_batch_get")
         return dict(X=X, U=U, z=z, lam=lam)
 
+    def _x0_list(self, x0s):
+        n = len(self.probs)
+        if x0s is None:
+            return [_f64(p.x0) for p in self.probs]
+        if len(x0s) != n:
+            raise ValueError(f"x0s: expected {n} entries, got {len(x0s)}")
+        return [_check_len(_f64(x), p.nx, f"x0s[{i}]") for i, (x, p) in enumerate(zip(x0s, self.probs))]
+
     def _x0_array(self, x0s):
         n = len(self.probs)
-        x0s = [_f64(p.x0) for p in self.probs] if x0s is None else [_f64(x) for x in x0s]
+        x0s = self._x0_list(x0s)
         return x0s, (_dp * n)(*[_ptr(x) for x in x0s])
 
     def phase_cycles(self, enable=True):

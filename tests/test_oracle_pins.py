@@ -337,3 +337,81 @@ def test_sls_tau_matches_gradient_of_tightening():
                 g[c] = (f(M[i] + e) - f(M[i] - e)) / (2 * hstep)
             t = tau[(k * N + j) * p.nc + i] if k < N else tau[N * N * p.nc + j * p.nf + i]
             np.testing.assert_allclose(g, t * M[i], rtol=1e-5, atol=1e-9)
+
+
+def _rho_case(primal_dominant):
+    """Small QP with general rows, a penalty and a starting iterate chosen so
+    that, after one x-update, the scaled primal residual dominates the scaled
+    dual residual (tight rows, small rho, start at z = y = 0) or the reverse
+    (a large rho that pins G xi to a start z which the projection then moves)."""
+    p = W.random_small(6, 3, 2, 4, 2, seed=21, lower=True)
+    m = p.m
+    rng = np.random.default_rng([21, 1])
+    if primal_dominant:
+        # rows that the first step violates by a lot
+        p.l = -0.02 * np.ones(m); p.u = 0.02 * np.ones(m)
+        z0 = np.zeros(m); y0 = np.zeros(m); rho = 0.7
+    else:
+        p.l = -0.3 * np.ones(m); p.u = 0.3 * np.ones(m)
+        z0 = rng.uniform(-0.15, 0.15, m); y0 = np.zeros(m); rho = 10.0
+    return p, z0, y0, rho
+
+
+def _scaled_residuals(p, rho, X, U, z_prev, z, y):
+    """The two scaled residuals of the rule, from the dense assembly: primal
+    |G xi - z| / max(|G xi|, |z|), dual rho |G^T (z - z_prev)| /
+    max(|H xi|, |G^T rho y|, |h|) (infinity norms)."""
+    H, h, Eq, e, Gm = dense.assemble(p)
+    xi = dense.join(p, X, U)
+    v = Gm @ xi
+    rp = np.max(np.abs(v - z))
+    rd = rho * np.max(np.abs(Gm.T @ (z - z_prev)))
+    ps = max(np.max(np.abs(v)), np.max(np.abs(z)))
+    ds = max(np.max(np.abs(H @ xi)), np.max(np.abs(Gm.T @ (rho * y))), np.max(np.abs(h)))
+    return rp / ps, rd / ds
+
+
+@pytest.mark.parametrize("primal_dominant", [True, False])
+def test_rho_rule_direction_magnitude_and_dual_continuity(primal_dominant):
+    """The adaptive penalty (Sec. IV-A, which defers to the residual-balancing
+    rule of OSQP): when the scaled primal residual dominates, rho must grow,
+    when the scaled dual residual dominates it must shrink, by the square root
+    of their ratio (the geometric mean that balances them), and the change
+    must leave the unscaled multiplier lambda = rho y untouched, so that the
+    iteration continues exactly as a fresh run at the new rho started from
+    (z, lambda / rho_new).  The residuals are measured here on the dense
+    assembly of the QP, not read from the oracle."""
+    p, z0, y0, rho = _rho_case(primal_dominant)
+    fixed = oracle.Settings(max_iter=1, adaptive=False)
+    one = oracle.qp_solve(p, rho=rho, tol=0.0, settings=fixed, z0=z0, y0=y0)
+    sp, sd = _scaled_residuals(p, rho, one["X"], one["U"], z0, one["z"], one["y"])
+    assert (sp > 10 * sd) if primal_dominant else (sd > 10 * sp)
+    # rule applied after iteration 1 (sigma = 1, always applied), then one more
+    # iteration at the new rho
+    adapt = oracle.Settings(max_iter=2, adaptive=True, sigma=1, rho_tol=1.0 + 1e-12)
+    two = oracle.qp_solve(p, rho=rho, tol=0.0, settings=adapt, z0=z0, y0=y0)
+    assert two["rho_updates"] == 1
+    rho_new = two["rho"]
+    assert (rho_new > rho) if primal_dominant else (rho_new < rho)
+    np.testing.assert_allclose(rho_new / rho, np.sqrt(sp / sd), rtol=1e-8)
+    # dual continuity: lambda = rho y kept, so a fresh iteration at rho_new from
+    # (z1, y1 rho / rho_new) reproduces the adaptive run's second iterate
+    fresh = oracle.qp_solve(p, rho=rho_new, tol=0.0, settings=fixed, z0=one["z"], y0=one["y"] * rho / rho_new)
+    for k in ("X", "U", "z", "y"):
+        np.testing.assert_allclose(two[k], fresh[k], rtol=1e-10, atol=1e-12)
+
+
+def test_rho_rule_band_and_clamp():
+    """No change while the proposed factor stays inside [1/rho_tol, rho_tol];
+    the proposal is clamped to [rho_min, rho_max]."""
+    p, z0, y0, rho = _rho_case(True)
+    one = oracle.qp_solve(p, rho=rho, tol=0.0, settings=oracle.Settings(max_iter=1, adaptive=False), z0=z0, y0=y0)
+    sp, sd = _scaled_residuals(p, rho, one["X"], one["U"], z0, one["z"], one["y"])
+    factor = np.sqrt(sp / sd)
+    wide = oracle.Settings(max_iter=2, adaptive=True, sigma=1, rho_tol=2 * factor)
+    r = oracle.qp_solve(p, rho=rho, tol=0.0, settings=wide, z0=z0, y0=y0)
+    assert r["rho_updates"] == 0 and r["rho"] == rho
+    cap = rho * factor / 3
+    clamp = oracle.Settings(max_iter=2, adaptive=True, sigma=1, rho_tol=1.0 + 1e-12, rho_max=cap)
+    r = oracle.qp_solve(p, rho=rho, tol=0.0, settings=clamp, z0=z0, y0=y0)
+    assert r["rho_updates"] == 1 and r["rho"] == cap

@@ -1,22 +1,27 @@
 """Benchmark of the MI355X ADMM / associative-scan QP solver.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload quadruped]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batch]
 
-A step is one complete QP solve (every factor epoch and every ADMM
-iteration, cold start z = y = 0, rho_0 = 1, OSQP-style rho adaptation) to a
-primal and dual residual of 1e-5, on a problem whose data is already resident
-in device memory (set up before the timed region).  The default workload is
-the quadruped-shaped time-varying QP: nx = 61, nu = 12, N = 128, 40 polytopic
-rows per stage.  Prints one JSON line.
+Default workload (the headline metric, warm-start vs cold-start ADMM): the
+uneven batch of 512 box-constrained LTV-QPs (nx in {12,36,61,75}, nu in
+{4,12,19}, N ~ U{16..512}) solved to a primal and dual residual of 1e-5 in one
+graph-replayed persistent launch.  A step is one whole batch: the K timed
+steps are run from a cold start (z = y = 0, rho = 1) and then from the learned
+warm start (prediction included); value is the warm-start solves/s and the
+cold-start figures sit beside it.  Problem data are resident in device memory
+before the timed region.
+
+Other workloads (--workload): quadruped | box | humanoid | long (one QP per
+step, cold start), sls, robust, sqp.
 
 The line carries
   * value      solves/s over the K timed steps;
-  * roofline   for the dominant kernel (the persistent ADMM iteration kernel):
-               algorithmic bytes of one cached iteration (each stage's fixed
-               operators read once per direction) times its iterations, over
-               its device time measured with HIP events on its stream;
-  * cpu_baseline  the FP64 CPU oracle (sequential Riccati ADMM, one thread) on
-               a bounded sample of the same workload.
+  * roofline   for the dominant kernel: algorithmic (floor) bytes of the
+               iterations it ran -- each stage's fixed operators read once per
+               direction -- over its device time measured with HIP events on
+               its stream;
+  * cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
+               (the batch: built for the host, OpenMP over the instances).
 """
 from __future__ import annotations
 
@@ -39,9 +44,14 @@ METRIC = "QP solves/s and ms/solve at 1e-5 residual; warm-start vs cold-start AD
 # kernel source it was taken on: reported while the hash of that source matches.
 K_ADMM_TRAFFIC = {"src_sha256_16": "1958d4f523f0555c", "sources": ("iterate.hip", "dev_common.hpp", "solver.hpp"),
                   "bytes_per_launch": 192072592.3}
+# The same for k_batch on the 512-instance batch (learned warm start).
+K_BATCH_TRAFFIC = {"src_sha256_16": "", "sources": ("batch.hip", "batch.hpp", "dev_common.hpp"),
+                   "bytes_per_launch": None}
 
 
 def kernel_traffic(entry):
+    if not entry.get("bytes_per_launch"):
+        return None
     import hashlib
     h = hashlib.sha256()
     for s in entry["sources"]:
@@ -298,18 +308,28 @@ def batch_floor_bytes(p):
 
 
 def bench_batch(args):
-    """512 box-constrained QPs of uneven shape (nx in {12,36,61,75}, nu in
-    {4,12,19}, N ~ U{16..512}) in one graph-replayed persistent launch, cold
-    start and (with the trained model in paper_2604_07644_amd/data/ws_box.bin)
-    learned warm start.  value: solves/s of the learned-warm-start solver
-    (prediction included in the timed region); the cold-start figures are in
-    config."""
+    """The uneven batch: 512 box-constrained QPs (nx in {12,36,61,75}, nu in
+    {4,12,19}, N ~ U{16..512}, per-instance bound scales) solved to a primal
+    and dual residual of 1e-5 in one graph-replayed persistent launch, from a
+    cold start and from the learned warm start (the trained model in
+    paper_2604_07644_amd/data/ws_box.bin; its prediction is inside the timed
+    region).  value: solves/s of the learned-warm-start solver; the cold-start
+    figures sit beside it in config.  roofline: k_batch, the floor bytes of
+    every iteration each instance ran (its stage operators read once per
+    direction) over the launch's device time (HIP events around the replayed
+    graph on the solver's stream, minus the prediction).  cpu_baseline: the
+    FP64 oracle compiled for this host (-O3 -march=native, OpenMP over the
+    instances, one sequential solve per thread) on every 16th instance of the
+    batch, cold start."""
     import torch
     from paper_2604_07644_amd import gsls, workloads as W
     count = 512
     probs = W.uneven_batch(count=count)
     stream = torch.cuda.current_stream().cuda_stream
     b = gsls.Batch(probs, stream=stream)
+    if args.gang is not None or args.park_share is not None:
+        b.set_schedule(gang=args.gang or 0, park_share=args.park_share or 0.0)
+    gang, share, park_at = b.schedule()
     model = os.path.join(ROOT, "paper_2604_07644_amd", "data", "ws_box.bin")
     ws = gsls.WarmStart(path=model, stream=stream) if os.path.exists(model) else None
 
@@ -318,27 +338,32 @@ def bench_batch(args):
             b.solve_ws(ws, tol=TOL) if warm else b.solve(tol=TOL)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        dev_ms, last = [], None
+        dev_ms, pred_ms, last = [], [], None
         for _ in range(args.steps):
             if warm:
-                last, ms, _ = b.solve_ws(ws, tol=TOL)
+                last, ms, msp = b.solve_ws(ws, tol=TOL)
             else:
                 last, ms = b.solve(tol=TOL)
+                msp = 0.0
             dev_ms.append(ms)
+            pred_ms.append(msp)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         it = np.array([r["iterations"] for r in last])
         work = float(sum(r["ms_factor"] + r["ms_iterate"] for r in last))
         return dict(solves_per_s=count * args.steps / wall, ms_per_step=1e3 * wall / args.steps,
-                    device_ms_per_batch=float(np.mean(dev_ms)), all_solved=all(r["status"] == gsls.SOLVED for r in last),
+                    device_ms_per_batch=float(np.mean(dev_ms)), predict_ms=float(np.mean(pred_ms)),
+                    solve_ms=float(np.mean(dev_ms) - np.mean(pred_ms)),
+                    all_solved=all(r["status"] == gsls.SOLVED for r in last),
                     iterations_mean=float(it.mean()), iterations_median=float(np.median(it)),
-                    iterations_max=int(it.max()), instance_ms_sum=work, iters=it)
+                    iterations_max=int(it.max()), instance_ms_sum=work,
+                    max_r_dyn=float(max(r["r_dyn"] for r in last)), iters=it)
 
     cold = run(False)
     warm = run(True) if ws is not None else None
     main = warm if warm is not None else cold
     byts = float(sum(batch_floor_bytes(p) * it for p, it in zip(probs, main["iters"])))
-    ms = main["device_ms_per_batch"]
+    ms = main["solve_ms"]
     achieved = byts / (ms * 1e-3) / 1e9
     for d in (cold, warm):
         if d is not None:
@@ -350,27 +375,33 @@ def bench_batch(args):
         "metric": METRIC, "value": main["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": main["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64 (bf16 MLP)",
-        "data": "synthetic (seeded generator)",
-        "config": {"workload": "batch of 512 box-constrained QPs, nx in {12,36,61,75}, nu in {4,12,19}, "
-                               "N ~ U{16..512}, one graph-replayed persistent launch",
+        "data": "synthetic (seeded generator; no robot models or datasets)",
+        "config": {"workload": "uneven batch: 512 box-constrained LTV-QPs, nx in {12,36,61,75}, nu in {4,12,19}, "
+                               "N ~ U{16..512}, one graph-replayed persistent launch, warm vs cold start",
                    "tol": TOL, "start": "learned warm" if warm is not None else "cold",
+                   "schedule": {"gang": gang, "park_share": share,
+                                "instances_eligible_for_gangs": int(np.sum(park_at < 2 ** 31 - 1))},
+                   "warm_vs_cold_speedup": (warm["solves_per_s"] / cold["solves_per_s"]) if warm else None,
                    "cold": cold, "warm": warm},
         "roofline": {"kernel": "k_batch (persistent batched ADMM)", "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "floor_bytes_per_batch": byts, "avg_launch_ms": ms},
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": kernel_traffic(K_BATCH_TRAFFIC),
+                     "floor_bytes_per_launch": byts, "avg_launch_ms": ms},
     }
     if not args.no_cpu:
-        import oracle
-        t0 = time.perf_counter()
-        n = 0
-        while True:
-            oracle.qp_solve(probs[n], rho=1.0, tol=TOL)
-            n += 1
+        import tempfile
+        from oracle import native
+        sample = probs[::16]
+        with tempfile.TemporaryDirectory() as td:
+            lib = native.load_native(td)
+            t0 = time.perf_counter()
+            it, threads = native.qp_solve_many(sample, rho=1.0, tol=TOL, lib=lib)
             el = time.perf_counter() - t0
-            if el >= args.cpu_budget or n >= count:
-                break
-        line["cpu_baseline"] = {"value": n / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
-                                "sample": f"the first {n} instances of the batch, cold start, tol {TOL:g}"}
+        line["cpu_baseline"] = {"value": len(sample) / el, "unit": "solves/s", "cores": threads, "kind": "oracle",
+                                "sample": f"every 16th instance of the batch ({len(sample)} QPs), cold start, "
+                                          f"tol {TOL:g}; FP64 Riccati ADMM built -O3 -march=native, OpenMP over "
+                                          f"instances on {threads} threads ({os.cpu_count()} logical CPUs)",
+                                "iterations_median": float(np.median(it)), "seconds": el}
     print(json.dumps(line), flush=True)
 
 
@@ -408,9 +439,11 @@ def cpu_baseline(p, budget_s=10.0, tol=TOL):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="quadruped")
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="batch")
+    ap.add_argument("--gang", type=int, default=None, help="batch: workgroups per gang (0 auto, 1 off)")
+    ap.add_argument("--park-share", type=float, default=None, help="batch: solo work budget (0 auto)")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
@@ -419,6 +452,11 @@ def main():
     ap.add_argument("--with-copy", action="store_true",
                     help="run the 256 MiB copy calibration before the benchmark, in the same process")
     args = ap.parse_args()
+    # a batch step is one whole 512-instance batch (about a second): fewer steps
+    if args.steps is None:
+        args.steps = 5 if args.workload == "batch" else 20
+    if args.warmup is None:
+        args.warmup = 1 if args.workload == "batch" else 3
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)

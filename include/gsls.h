@@ -98,6 +98,11 @@ typedef struct gsls_settings {
                             one stage per chunk, at most 256 chunks) */
   int32_t chunks_iter;   /* horizon chunks (workgroups) for the iteration      [0]
                             scans (0 = auto: one stage per workgroup, at most 256) */
+  int32_t refresh;       /* mixed precision: the x-update is evaluated on the  [0]
+                            increment of w = y - z and accumulated in FP64, in
+                            full after each factor epoch and, if refresh > 0,
+                            at every iteration count that is a multiple of
+                            refresh (bounds the FP32 drift of the accumulators) */
 } gsls_settings;
 
 /* Outcome of one solve. */
@@ -117,6 +122,10 @@ typedef struct gsls_result {
                             converge within the warm budget and was re-solved
                             from a cold start (its iterations include both)    */
   int32_t reserved;
+  double r_dyn;          /* max_k |x_{k+1} - A_k x_k - B_k u_k - b_k|_inf of the
+                            returned iterate, evaluated in FP64 on the working-
+                            precision stage data (mixed precision: non-zero at
+                            the level of FP32 rounding)                        */
 } gsls_result;
 
 typedef struct gsls_qp gsls_qp;
@@ -350,6 +359,25 @@ int gsls_qp_solve_batch(gsls_batch* b, const double* const* x0, const double* rh
 int gsls_batch_get(gsls_batch* b, int32_t index, double* X, double* U, double* z, double* lambda);
 
 void gsls_batch_free(gsls_batch* b);
+
+/* Schedule of the batched launch (Sec. IV-A: the horizon of one instance is
+ * split into chunks whose affine maps are composed by associative scans).
+ * Every instance starts on one workgroup; an instance with N >= 2 gang that
+ * has not converged after park_at iterations is continued by a gang of
+ * `gang` workgroups, each owning N / gang consecutive stages (chunk fold,
+ * recursive doubling over the chunk transfer maps, re-run from the exact
+ * entry).  park_at is the iteration count at which the instance's estimated
+ * solo work reaches park_share times one workgroup's share of the batch
+ * (every instance at 100 iterations); it depends on the shapes only, so a
+ * replay takes the same path.
+ *  gang: 0 = automatic (16), 1 = no gangs, 2..32 (at most half the grid).
+ *  park_share: > 0, or 0 = automatic (0.5).
+ * Drops the captured launch (the next solve captures a new one). */
+int gsls_batch_set_schedule(gsls_batch* b, int32_t gang, double park_share);
+
+/* Current schedule; park_at (nullable) receives count entries (2^31 - 1:
+ * the instance never leaves its solo workgroup). */
+int gsls_batch_get_schedule(gsls_batch* b, int32_t* gang, double* park_share, int32_t* park_at);
 
 /* Diagnostics: enable != 0 turns on per-phase device-clock counters of the
  * batched iterations (summed over instances; they add one barrier per

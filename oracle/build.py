@@ -13,12 +13,25 @@ OUT = os.path.join(HERE, "_oracle.so")
 
 
 def build(verbose=False) -> str:
-    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c99", "-o", OUT + ".tmp", SRC, "-lm"]
+    """Portable build used by the tests (no host-specific instructions, so
+    the object runs on any x86-64 host it is copied to)."""
+    cmd = ["gcc", "-O3", "-fPIC", "-shared", "-std=c99", "-o", OUT + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
     os.replace(OUT + ".tmp", OUT)
     return OUT
+
+
+def build_native(outdir, verbose=False) -> str:
+    """Build for the host it runs on (-O3 -march=native, OpenMP) into outdir:
+    the benchmark's CPU baseline compiles this copy on the machine it times."""
+    out = os.path.join(outdir, "_oracle_native.so")
+    cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", out, SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    return out
 
 
 if __name__ == "__main__":

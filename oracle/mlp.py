@@ -57,23 +57,15 @@ def unflatten(theta, sizes=SIZES):
     return out
 
 
-def forward(theta, X, sizes=SIZES, store=None):
-    """Returns Y and the list of layer inputs (X, h1, h2, h3).  ``store``, if
-    given, is applied to each hidden activation as it is kept (the storage
-    precision of an implementation that keeps activations narrower than
-    FP64; the identity when None)."""
+def forward(theta, X, sizes=SIZES):
+    """Returns Y and the list of layer inputs (X, h1, h2, h3)."""
     layers = unflatten(np.asarray(theta, dtype=np.float64), sizes)
     h = np.asarray(X, dtype=np.float64)
     acts = []
     for i, (W, b) in enumerate(layers):
         acts.append(h)
         a = h @ W + b
-        if i + 1 < len(layers):
-            h = np.maximum(a, 0.0)
-            if store is not None:
-                h = store(h)
-        else:
-            h = a
+        h = np.maximum(a, 0.0) if i + 1 < len(layers) else a
     return h, acts
 
 
@@ -82,19 +74,16 @@ def loss(theta, X, T, M, sizes=SIZES):
     return float(np.sum(M * (Y - T) ** 2) / np.sum(M))
 
 
-def loss_grad(theta, X, T, M, sizes=SIZES, store=None):
+def loss_grad(theta, X, T, M, sizes=SIZES):
     """Loss and its gradient with respect to the flat parameter vector, by
     the chain rule through the layers (reverse mode).  The back-propagated
     quantities are carried as 2 M (Y - T) and its images, and every gradient
-    is divided by sum(M) at the end (the same numbers as dividing first).
-    ``store`` (optional) is applied to the hidden activations and to each
-    back-propagated delta as it is kept."""
+    is divided by sum(M) at the end (the same numbers as dividing first)."""
     layers = unflatten(np.asarray(theta, dtype=np.float64), sizes)
-    keep = (lambda v: v) if store is None else store
-    Y, acts = forward(theta, X, sizes, store)
+    Y, acts = forward(theta, X, sizes)
     cnt = float(np.sum(M))
     L = float(np.sum(M * (Y - T) ** 2) / cnt)
-    dA = keep(2.0 * M * (Y - T))              # dL/d(pre-activation) of the last layer, times sum(M)
+    dA = 2.0 * M * (Y - T)                    # dL/d(pre-activation) of the last layer, times sum(M)
     grads = []
     for i in range(len(layers) - 1, -1, -1):
         W, _ = layers[i]
@@ -102,7 +91,7 @@ def loss_grad(theta, X, T, M, sizes=SIZES, store=None):
         grads.append((h.T @ dA / cnt, dA.sum(axis=0) / cnt))
         if i > 0:
             dh = dA @ W.T
-            dA = keep(dh * (h > 0.0))         # h = relu(a) of layer i-1: relu'(a) = [h > 0]
+            dA = dh * (h > 0.0)               # h = relu(a) of layer i-1: relu'(a) = [h > 0]
     grads.reverse()
     flat = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
     return L, flat

@@ -134,3 +134,38 @@ def sls_tau(prob, lam, Phi_x, Phi_u, eps=1e-8):
     arrs = [_c(prob.C), _c(prob.D), _c(prob.CN, (nf, nx)), _c(lam), _c(Phi_x), _c(Phi_u)]
     lib.oracle_sls_tau(N, nx, nu, nc, nf, *[_p(a) for a in arrs], ct.c_double(eps), _p(tau))
     return tau
+
+
+def qp_solve_many(probs, rho=1.0, tol=1e-6, settings: Settings | None = None, lib=None):
+    """Cold-start Riccati ADMM of every instance (oracle_qp_solve_many: OpenMP
+    over the instances when the library was built with it).  lib: a ctypes
+    library (e.g. from load_native); default the portable build.  Returns
+    (iterations [count], threads)."""
+    lib = lib or _load()
+    s = settings or Settings()
+    n = len(probs)
+    dims = np.zeros(5 * n, dtype=np.int32)
+    keep = []
+    ptrs = (_dp * (14 * n))()
+    for c, p in enumerate(probs):
+        dims[5 * c:5 * c + 5] = (p.N, p.nx, p.nu, p.nc, p.nf)
+        arrs = [_c(p.A), _c(p.B), _c(p.b), _c(p.Q), _c(p.R), _c(p.S), _c(p.q), _c(p.r), _c(p.C), _c(p.D),
+                _c(p.CN, (p.nf, p.nx)), _c(p.l), _c(p.u), _c(p.x0)]
+        keep.append(arrs)
+        for k, a in enumerate(arrs):
+            ptrs[14 * c + k] = _p(a)
+    info = np.zeros(8 * n)
+    lib.oracle_qp_solve_many.restype = ct.c_int
+    th = lib.oracle_qp_solve_many(int(n), dims.ctypes.data_as(ct.POINTER(ct.c_int32)), ptrs, ct.c_double(rho),
+                                  ct.c_double(tol), int(s.max_iter), int(bool(s.adaptive)), int(s.sigma),
+                                  ct.c_double(s.rho_min), ct.c_double(s.rho_max), ct.c_double(s.rho_tol),
+                                  _p(info))
+    return info.reshape(n, 8)[:, 0].astype(int), int(th)
+
+
+def load_native(outdir):
+    """The oracle compiled for this host (-O3 -march=native, OpenMP) into
+    outdir, as a ctypes library."""
+    from .build import build_native
+    return ct.CDLL(build_native(outdir))
+

@@ -419,6 +419,47 @@ done:;
   return status;
 }
 
+/*
+ * Batch driver of the CPU baseline: `count` independent instances solved by
+ * oracle_qp_solve from a cold start, in parallel over the host cores when
+ * compiled with OpenMP (one instance per thread at a time, dynamic schedule;
+ * each solve stays sequential).  dims[5c..5c+4] = N, nx, nu, nc, nf of
+ * instance c; ptrs[14c..14c+13] = A, B, b, Q, R, S, q, r, C, D, CN, l, u, x0;
+ * info[8c..8c+7] as for oracle_qp_solve.  The solutions are not returned.
+ * Returns the number of threads that ran.
+ */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int oracle_qp_solve_many(int count, const int* dims, const double* const* ptrs, double rho0, double tol,
+                         int max_iter, int adaptive, int sigma, double rho_min, double rho_max, double rho_tol,
+                         double* info) {
+  int threads = 1;
+#ifdef _OPENMP
+#pragma omp parallel
+  {
+#pragma omp single
+    threads = omp_get_num_threads();
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int c = 0; c < count; ++c) {
+    const int* d = dims + 5 * (size_t)c;
+    const double* const* a = ptrs + 14 * (size_t)c;
+    const int N = d[0], nx = d[1], nu = d[2], nc = d[3], nf = d[4];
+    const size_t m = (size_t)N * nc + nf;
+    double* X = malloc(sizeof(double) * (size_t)(N + 1) * nx);
+    double* U = malloc(sizeof(double) * ((size_t)N * nu + 1));
+    double* z = malloc(sizeof(double) * (m + 1));
+    double* y = malloc(sizeof(double) * (m + 1));
+    oracle_qp_solve(N, nx, nu, nc, nf, a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7], a[8], a[9], a[10], a[11],
+                    a[12], a[13], rho0, tol, max_iter, adaptive, sigma, rho_min, rho_max, rho_tol, NULL, NULL, X, U,
+                    z, y, info + 8 * (size_t)c);
+    free(X); free(U); free(z); free(y);
+  }
+  return threads;
+}
+
 /* ------------------------------------------------------------------- SLS */
 
 static size_t offx(int N, int j) { return (size_t)j * N - (size_t)j * (j - 1) / 2; }

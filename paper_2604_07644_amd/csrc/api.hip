@@ -355,12 +355,13 @@ struct Solver : SolverBase {
       a.ip.P = Pi; a.ip.nlev = nlev; a.ip.rho = cur; a.ip.tol = tol; a.ip.it0 = it;
       a.ip.max_iter = st.max_iter; a.ip.adaptive = st.adaptive_rho; a.ip.sigma = st.sigma;
       a.ip.rho_min = st.rho_min; a.ip.rho_max = st.rho_max; a.ip.rho_tol = st.rho_tol;
-      a.ip.hnorm = hnorm; a.ip.stamp0 = stamp;
+      a.ip.hnorm = hnorm; a.ip.stamp0 = stamp; a.ip.refresh = st.refresh;
       if (hipMemsetAsync(ll.abort, 0, sizeof(int), stream) != hipSuccess) return GSLS_ERR_HIP;
       if (hipMemsetAsync(ctl, 0, sizeof(IterCtl), stream) != hipSuccess) return GSLS_ERR_HIP;
       if (hipEventRecord(ev[2], stream) != hipSuccess) return GSLS_ERR_HIP;
       if ((rc = launch_admm<T>(a, stream))) return rc;
       if (hipEventRecord(ev[3], stream) != hipSuccess) return GSLS_ERR_HIP;
+      if ((rc = launch_rdyn<T>(pb, X, U, ctl, stream))) return rc;
       if (hipMemcpyAsync(ctl_h, ctl, sizeof(IterCtl), hipMemcpyDeviceToHost, stream) != hipSuccess) return GSLS_ERR_HIP;
       if (hipStreamSynchronize(stream) != hipSuccess) return GSLS_ERR_HIP;
       float t = 0.f;
@@ -368,7 +369,7 @@ struct Solver : SolverBase {
       ms_i += t;
       stamp += (uint32_t)(ctl_h->it - it) + 2;
       it = ctl_h->it;
-      r.r_p = ctl_h->r_p; r.r_d = ctl_h->r_d;
+      r.r_p = ctl_h->r_p; r.r_d = ctl_h->r_d; r.r_dyn = ctl_h->r_dyn;
       const int s = ctl_h->status;
       if (s == 5) return GSLS_ERR_HIP;
       if (s == 4) {
@@ -769,6 +770,7 @@ void gsls_default_settings(gsls_settings* s) {
   s->rho_tol = 5.0;
   s->chunks_epoch = 0;
   s->chunks_iter = 0;
+  s->refresh = 0;
 }
 
 const char* gsls_strerror(int code) {
@@ -791,7 +793,7 @@ namespace gsls {
 int check_settings(const gsls_settings* s) {
   if (s->precision != GSLS_MIXED && s->precision != GSLS_FP64) return GSLS_ERR_INVALID_ARG;
   if (s->max_iter < 1 || s->sigma < 1 || !(s->rho_min > 0) || !(s->rho_max >= s->rho_min) ||
-      !(s->rho_tol > 1.0) || s->chunks_epoch < 0 || s->chunks_iter < 0 || s->chunks_iter > 256)
+      !(s->rho_tol > 1.0) || s->chunks_epoch < 0 || s->chunks_iter < 0 || s->chunks_iter > 256 || s->refresh < 0)
     return GSLS_ERR_INVALID_ARG;
   return GSLS_OK;
 }

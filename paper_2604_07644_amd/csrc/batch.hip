@@ -31,6 +31,9 @@ namespace gsls {
 
 constexpr int kBV = 128;       // work-vector length (>= nx + nu, >= nc)
 constexpr int kBatchMaxNxu = 96;
+constexpr int kGangMax = 32;          // workgroups per gang (6 kGangMax <= kWG: residual exchange)
+constexpr int kGangAuto = 16;
+constexpr double kParkShareAuto = 0.5;
 
 __host__ __device__ inline int bodd(int x) { return x | 1; }
 
@@ -373,20 +376,28 @@ struct PhaseMark {
   }
 };
 
-// Backward pass of one cached iteration (Sec. IV-A): p_N = cst q_N + rho C_N^T dw_N,
-// then per stage k = N-1..0, from the stage packet in LDS,
+// Backward pass of one cached iteration (Sec. IV-A) over the stages [s, e):
+// p_N = cst q_N + rho C_N^T dw_N when e = N (else p_e is the caller's entry
+// in V.g, or zero in fold mode), then per stage k = e-1..s, from the stage
+// packet in LDS,
 //   F^T [p; r_hat] = [Abar^T p + K^T r_hat; B^T p + r_hat]  (F = [[Abar, B], [K, I]]),
 //   p_k = Abar^T p + K^T r_hat + cst (q_k + ev_k) + rho C_k^T dw,
 //   k_k = -Gamma (B^T p + r_hat + cst fv_k),  r_hat = cst r_k + rho D_k^T dw,
 // with dw the increment of w = y - z (w itself on a full evaluation, cst = 1).
-// Writes k_k to the feed-forward store.  Thread r handles constraint row r of
-// every stage (so its global reads are its own writes: LDS-only barriers).
+// Writes k_k to the feed-forward store and w to the previous-w store.  Fold
+// mode (a chunk of a horizon shared by several workgroups) runs the p
+// recurrence alone from a zero entry and writes nothing; p_s is left in V.g.
+// Thread r handles constraint row r of every stage (so its global reads are
+// its own writes: LDS-only barriers).
 template <bool BOX>
 __device__ __attribute__((noinline)) void batch_backward(const BInst* __restrict__ Ip,
                                                          const BatchArgs* __restrict__ ag, float fr, bool full,
-                                                         LDS char* base) {
+                                                         LDS char* base, int s, int e, bool fold) {
   Ip = uniform_ptr(Ip);
   ag = uniform_ptr(ag);
+  s = uniform_int(s);
+  e = uniform_int(e);
+  fold = uniform_int(fold ? 1 : 0) != 0;
   const BInst& I = *Ip;
   const BatchArgs& a = *ag;
   const int N = I.N, nx = I.nx, nu = I.nu, nc = I.nc, nf = I.nf, nxu = nx + nu;
@@ -404,31 +415,39 @@ __device__ __attribute__((noinline)) void batch_backward(const BInst* __restrict
   const float cst = full ? 1.f : 0.f;
   const int t = tid();
   PhaseMark mark{V.pc, a.prof != nullptr};
-  for (int r = t; r < nf; r += kWG) {
-    const size_t gr = (size_t)N * nc + r;
-    const double w = ys[gr] - zs[gr];
-    V.wv[r] = (float)(full ? w : w - wprev[gr]);
-    wprev[gr] = w;
+  if (e == N) {
+    for (int r = t; r < nf; r += kWG) {
+      const size_t gr = (size_t)N * nc + r;
+      const double w = ys[gr] - zs[gr];
+      V.wv[r] = (float)(full ? w : w - wprev[gr]);
+      if (!fold) wprev[gr] = w;
+    }
+    lds_barrier();
+    if (nf > 0 && !BOX) lite_gemv_t(nf, nx, (const float*)(fp + I.oCN), nx, V.wv, V.tv, V.part);
+    for (int j = t; j < nx; j += kWG) {
+      const float cw = nf > 0 ? (BOX ? V.wv[j] : V.tv[j]) : 0.f;
+      V.g[j] = cst * fp[I.oq + (size_t)N * nx + j] + fr * cw;
+    }
+  } else if (fold) {
+    for (int j = t; j < nx; j += kWG) V.g[j] = 0.f;
   }
-  lds_barrier();
-  if (nf > 0 && !BOX) lite_gemv_t(nf, nx, (const float*)(fp + I.oCN), nx, V.wv, V.tv, V.part);
-  for (int j = t; j < nx; j += kWG) {
-    const float cw = nf > 0 ? (BOX ? V.wv[j] : V.tv[j]) : 0.f;
-    V.g[j] = cst * fp[I.oq + (size_t)N * nx + j] + fr * cw;
+  if (s >= e) {
+    lds_barrier();
+    return;
   }
-  pk_dma_issue(pkt + (size_t)(N - 1) * pst, pst, V.buf[0]);
+  pk_dma_issue(pkt + (size_t)(e - 1) * pst, pst, V.buf[0]);
   double ry = 0.0, rz = 0.0, rw = 0.0;
   if (t < nc) {
-    const size_t gr = (size_t)(N - 1) * nc + t;
+    const size_t gr = (size_t)(e - 1) * nc + t;
     ry = ys[gr]; rz = zs[gr]; rw = wprev[gr];
   }
   pk_dma_wait();
   lds_barrier();
   int cb = 0;
-  for (int i = N - 1; i >= 0; --i) {
+  for (int i = e - 1; i >= s; --i) {
     LDS float* P = V.buf[cb];
     double ny = 0.0, nz = 0.0, nw = 0.0;
-    if (i > 0) {
+    if (i > s) {
       pk_dma_issue(pkt + (size_t)(i - 1) * pst, pst, V.buf[cb ^ 1]);
       if (t < nc) {
         const size_t gr = (size_t)(i - 1) * nc + t;
@@ -439,7 +458,7 @@ __device__ __attribute__((noinline)) void batch_backward(const BInst* __restrict
     if (t < nc) {
       const double w = ry - rz;
       V.wv[t] = (float)(full ? w : w - rw);
-      wprev[(size_t)i * nc + t] = w;
+      if (!fold) wprev[(size_t)i * nc + t] = w;
     }
     lds_barrier();
     mark(1);
@@ -463,15 +482,19 @@ __device__ __attribute__((noinline)) void batch_backward(const BInst* __restrict
     }
     lds_barrier();
     mark(2);
-    lite_gemv_t(nxu, nxu, (const LDS float*)(P + pk.F), pk.ldF, V.xz, V.g2, V.part);
+    lite_gemv_t(nxu, fold ? nx : nxu, (const LDS float*)(P + pk.F), pk.ldF, V.xz, V.g2, V.part);
     mark(3);
-    for (int j = t; j < nxu; j += kWG) {
-      if (j < nx) V.g[j] = V.g2[j] + V.wv2[j];
-      else V.tu[j - nx] = V.g2[j] + cst * P[pk.fv + (j - nx)];
+    if (fold) {
+      for (int j = t; j < nx; j += kWG) V.g[j] = V.g2[j] + V.wv2[j];
+    } else {
+      for (int j = t; j < nxu; j += kWG) {
+        if (j < nx) V.g[j] = V.g2[j] + V.wv2[j];
+        else V.tu[j - nx] = V.g2[j] + cst * P[pk.fv + (j - nx)];
+      }
+      lds_barrier();
+      lite_gemv_t(nu, nu, (const LDS float*)(P + pk.Gam), nu, V.tu, V.g2, V.part);
+      for (int j = t; j < nu; j += kWG) kff[(size_t)i * nu + j] = -V.g2[j];
     }
-    lds_barrier();
-    lite_gemv_t(nu, nu, (const LDS float*)(P + pk.Gam), nu, V.tu, V.g2, V.part);
-    for (int j = t; j < nu; j += kWG) kff[(size_t)i * nu + j] = -V.g2[j];
     mark(4);
     ry = ny; rz = nz; rw = nw;
     pk_dma_wait();
@@ -482,12 +505,15 @@ __device__ __attribute__((noinline)) void batch_backward(const BInst* __restrict
 }
 
 // |H xi| on the accumulated iterate (rho rule's dual scale): max over the
-// stages of |Q x + S^T u| and |S x + R u| (Q_N x_N at the terminal stage).
+// stages [s, e) of |Q x + S^T u| and |S x + R u| (and Q_N x_N when e = N).
 // Returns the workgroup maximum.
 __device__ __attribute__((noinline)) double batch_hxi(const BInst* __restrict__ Ip,
-                                                      const BatchArgs* __restrict__ ag, LDS char* base) {
+                                                      const BatchArgs* __restrict__ ag, LDS char* base, int s,
+                                                      int e) {
   Ip = uniform_ptr(Ip);
   ag = uniform_ptr(ag);
+  s = uniform_int(s);
+  e = uniform_int(e);
   const BInst& I = *Ip;
   const BatchArgs& a = *ag;
   const int N = I.N, nx = I.nx, nu = I.nu, nc = I.nc, nf = I.nf;
@@ -498,7 +524,8 @@ __device__ __attribute__((noinline)) double batch_hxi(const BInst* __restrict__ 
   const GLB double* U = (const GLB double*)(a.dp + I.oU);
   const int t = tid();
   double hx = 0.0;
-  for (int i = 0; i <= N; ++i) {
+  const int last = e == N ? N : e - 1;
+  for (int i = s; i <= last; ++i) {
   const bool term = i == N;
   for (int j = t; j < nx; j += kWG) V.tv[j] = (float)X[(size_t)i * nx + j];
   if (!term)
@@ -518,19 +545,27 @@ __device__ __attribute__((noinline)) double batch_hxi(const BInst* __restrict__ 
   return wg_max_d(hx, V.red);
 }
 
-// Forward pass of one cached iteration: x_0 = cst x0, per stage
-// F [x; k] = [Abar x + B k; K x + k] gives u_k and x_{k+1} (+ cst b_k), the
-// constraint values v = G [x; u] (box rows: v = [x; u]), then the projection
-// z+ = clip(v + y, l, u), the scaled dual y+ = y + v - z+, and the residual
-// terms.  x, u, v accumulate in FP64 (increments after the first evaluation).
-// Returns, reduced over the workgroup, r_p, r_d and (rho-rule iterations)
-// |v|, |z|, |H xi|, |G^T lambda| / rho in out[0..5] (LDS).
+// Forward pass of one cached iteration over the stages [s, e) (and the
+// terminal stage when e = N) from the entry x_s in V.xz[0..nx) (set by the
+// caller: cst x0 for s = 0): per stage F [x; k] = [Abar x + B k; K x + k]
+// gives u_k and x_{k+1} (+ cst b_k), the constraint values v = G [x; u] (box
+// rows: v = [x; u]), then the projection z+ = clip(v + y, l, u), the scaled
+// dual y+ = y + v - z+, and the residual terms.  x, u, v accumulate in FP64
+// (increments after the first evaluation).  Returns, reduced over the
+// workgroup, r_p, r_d and (rho-rule iterations) |v|, |z|, |H xi|,
+// |G^T lambda| / rho of its stages in out[0..5] (LDS).
+// A chunk that ends before the horizon (e < N) leaves x_e in V.xz[0..nx).
+// Fold mode runs the x recurrence alone and writes nothing: x_e is left in
+// V.xz[0..nx).
 template <bool BOX>
 __device__ __attribute__((noinline)) void batch_forward(const BInst* __restrict__ Ip,
                                                         const BatchArgs* __restrict__ ag, double rho, bool full,
-                                                        bool sigma_it, LDS char* base) {
+                                                        bool sigma_it, LDS char* base, int s, int e, bool fold) {
   Ip = uniform_ptr(Ip);
   ag = uniform_ptr(ag);
+  s = uniform_int(s);
+  e = uniform_int(e);
+  fold = uniform_int(fold ? 1 : 0) != 0;
   const BInst& I = *Ip;
   const BatchArgs& a = *ag;
   const int N = I.N, nx = I.nx, nu = I.nu, nc = I.nc, nf = I.nf, nxu = nx + nu;
@@ -541,6 +576,33 @@ __device__ __attribute__((noinline)) void batch_forward(const BInst* __restrict_
   const float* fp = a.fp;
   double* dp = a.dp;
   const float* pkt = fp + I.oPk;
+  const GLB float* kff = (const GLB float*)(fp + I.okff);
+  const float cst = full ? 1.f : 0.f;
+  const int t = tid();
+  if (fold) {
+    // (each stage's feed-forward term is read one stage ahead, with the
+    // next packet's copy)
+    if (s < e) pk_dma_issue(pkt + (size_t)s * pst, pst, V.buf[0]);
+    float kf = (s < e && t < nu) ? kff[(size_t)s * nu + t] : 0.f;
+    pk_dma_wait();
+    lds_barrier();
+    int cb = 0;
+    for (int i = s; i < e; ++i) {
+      LDS float* P = V.buf[cb];
+      if (t < nu) V.xz[nx + t] = kf;
+      if (i + 1 < e) {
+        pk_dma_issue(pkt + (size_t)(i + 1) * pst, pst, V.buf[cb ^ 1]);
+        if (t < nu) kf = kff[(size_t)(i + 1) * nu + t];
+      }
+      lds_barrier();
+      lite_gemv_n(nx, nxu, (const LDS float*)(P + pk.F), pk.ldF, V.xz, V.g2, V.part, false);
+      for (int j = t; j < nx; j += kWG) V.xz[j] = V.g2[j] + cst * P[pk.b + j];
+      pk_dma_wait();
+      lds_barrier();
+      cb ^= 1;
+    }
+    return;
+  }
   GLB double* ys = (GLB double*)(dp + I.oy);
   GLB double* zs = (GLB double*)(dp + I.oz);
   GLB double* vacc = (GLB double*)(dp + I.ov);
@@ -548,28 +610,35 @@ __device__ __attribute__((noinline)) void batch_forward(const BInst* __restrict_
   const GLB double* us = (const GLB double*)(dp + I.ou);
   GLB double* X = (GLB double*)(dp + I.oX);
   GLB double* U = (GLB double*)(dp + I.oU);
-  const GLB float* kff = (const GLB float*)(fp + I.okff);
-  const GLB float* x0 = (const GLB float*)(fp + I.ox0);
-  const float cst = full ? 1.f : 0.f;
-  const int t = tid();
   PhaseMark mark{V.pc, a.prof != nullptr};
   double rp = 0.0, rd = 0.0, vmax = 0.0, zmax = 0.0, hx = 0.0, gl = 0.0;
-  for (int j = t; j < nx; j += kWG) V.xz[j] = cst * x0[j];
-  pk_dma_issue(pkt, pst, V.buf[0]);
+  const int last = e == N ? N : e - 1;   // last stage processed
+  if (s < e) pk_dma_issue(pkt + (size_t)s * pst, pst, V.buf[0]);
   double sv = 0.0, sy = 0.0, sz = 0.0, sl = 0.0, su = 0.0, sX = 0.0, sU = 0.0;
-  if (t < nc) { sv = vacc[t]; sy = ys[t]; sz = zs[t]; sl = ls[t]; su = us[t]; }
-  if (t < nx) sX = X[t];
-  if (t < nu) sU = U[t];
+  {
+    const int nr0 = (s == N) ? nf : nc;
+    if (t < nr0) {
+      const size_t gr = (size_t)s * nc + t;
+      sv = vacc[gr]; sy = ys[gr]; sz = zs[gr]; sl = ls[gr]; su = us[gr];
+    }
+    if (t < nx) sX = X[(size_t)s * nx + t];
+    if (s < N && t < nu) sU = U[(size_t)s * nu + t];
+  }
+  float sK = (s < N && t < nu) ? kff[(size_t)s * nu + t] : 0.f;
   pk_dma_wait();
   lds_barrier();
   int cb = 0;
-  for (int i = 0; i <= N; ++i) {
+  for (int i = s; i <= last; ++i) {
     const bool term = (i == N);
     const int nr = term ? nf : nc;
     LDS float* P = V.buf[cb];
     double nv = 0.0, ny = 0.0, nz = 0.0, nl = 0.0, nu_ = 0.0, nX = 0.0, nU = 0.0;
-    if (i + 1 < N) pk_dma_issue(pkt + (size_t)(i + 1) * pst, pst, V.buf[cb ^ 1]);
-    if (i + 1 <= N) {
+    // the stage's feed-forward term was read one stage ahead
+    if (!term && t < nu) V.xz[nx + t] = sK;
+    if (i + 1 < e) pk_dma_issue(pkt + (size_t)(i + 1) * pst, pst, V.buf[cb ^ 1]);
+    float nK = 0.f;
+    if (i + 1 < N && i + 1 <= last && t < nu) nK = kff[(size_t)(i + 1) * nu + t];
+    if (i + 1 <= last) {
       const int nr1 = (i + 1 == N) ? nf : nc;
       if (t < nr1) {
         const size_t gr = (size_t)(i + 1) * nc + t;
@@ -581,7 +650,6 @@ __device__ __attribute__((noinline)) void batch_forward(const BInst* __restrict_
     if (t < nx) X[(size_t)i * nx + t] = full ? (double)V.xz[t] : sX + (double)V.xz[t];
     mark(6);
     if (!term) {
-      for (int j = t; j < nu; j += kWG) V.xz[nx + j] = kff[(size_t)i * nu + j];
       lds_barrier();
       mark(7);
       lite_gemv_n(nxu, nxu, (const LDS float*)(P + pk.F), pk.ldF, V.xz, V.g2, V.part, false);
@@ -615,8 +683,8 @@ __device__ __attribute__((noinline)) void batch_forward(const BInst* __restrict_
       const double yn = sy + v - zn;
       zs[gr] = zn;
       ys[gr] = yn;
-      const double e = fabs(v - zn);
-      rp = (e > rp || e != e) ? e : rp;
+      const double er = fabs(v - zn);
+      rp = (er > rp || er != er) ? er : rp;
       vmax = fmax(vmax, fabs(v));
       zmax = fmax(zmax, fabs(zn));
       V.wv[t] = (float)(zn - sz);
@@ -649,7 +717,11 @@ __device__ __attribute__((noinline)) void batch_forward(const BInst* __restrict_
     mark(10);
     if (term) break;
     for (int j = t; j < nx; j += kWG) V.xz[j] = V.g2[j] + cst * P[pk.b + j];
-    sv = nv; sy = ny; sz = nz; sl = nl; su = nu_; sX = nX; sU = nU;
+    if (i == last) {   // a chunk that ends before the horizon: x_e stays in V.xz
+      lds_barrier();
+      break;
+    }
+    sv = nv; sy = ny; sz = nz; sl = nl; su = nu_; sX = nX; sU = nU; sK = nK;
     pk_dma_wait();
     lds_barrier();
     mark(11);
@@ -661,21 +733,53 @@ __device__ __attribute__((noinline)) void batch_forward(const BInst* __restrict_
     vmax = wg_max_d(vmax, V.red);
     zmax = wg_max_d(zmax, V.red);
     gl = wg_max_d(gl, V.red);
-    hx = batch_hxi(Ip, ag, base);   // on the x, u just accumulated
+    hx = batch_hxi(Ip, ag, base, s, e);   // on the x, u just accumulated
   }
   LDS double* out = V.red + kWG;   // the reduction buffer holds kWG + 8 doubles
   if (t == 0) { out[0] = rp; out[1] = rd; out[2] = vmax; out[3] = zmax; out[4] = hx; out[5] = gl; }
   lds_barrier();
 }
 
-// ADMM iterations of one instance at fixed rho.  Returns 1 solved, 2 max_iter,
-// 3 numerical, 4 rho change (new rho in *rho_new).
+// Decision after one ADMM iteration from the reduced residual terms
+// o = (r_p, r_d, |v|, |z|, |H xi|, |G^T lambda| / rho): 0 continue, 1 solved,
+// 2 iteration limit, 3 numerical, 4 rho change (OSQP rule every sigma
+// iterations, new rho in *rn).
+__device__ inline int admm_decide(const BatchArgs& a, double rho, int it, int max_iter, bool sigma_it,
+                                  double hnorm, const double o[6], double* rn) {
+  const double rp = o[0], rd = o[1];
+  if (rp != rp || rd != rd || isinf(rp) || isinf(rd)) return 3;
+  if (rp <= a.tol && rd <= a.tol) return 1;
+  if (it >= max_iter) return 2;
+  if (sigma_it) {
+    const double ps = fmax(o[2], o[3]), ds = fmax(fmax(o[4], o[5]), hnorm);
+    const double ratio = (rp / (ps + 1e-10)) / (rd / (ds + 1e-10) + 1e-10);
+    const double r = fmin(fmax(rho * sqrt(ratio), a.rho_min), a.rho_max);
+    if (r > rho * a.rho_tol || r < rho / a.rho_tol) {
+      *rn = r;
+      return 4;
+    }
+  }
+  return 0;
+}
+
+// max(|q|, |r|) over the instance (the rho rule's dual scale floor).
+__device__ inline double batch_hnorm(const BInst& I, const float* fp, LDS double* red) {
+  double h = 0.0;
+  for (int e = tid(); e < (I.N + 1) * I.nx; e += kWG) h = fmax(h, fabs((double)fp[I.oq + e]));
+  for (int e = tid(); e < I.N * I.nu; e += kWG) h = fmax(h, fabs((double)fp[I.orr + e]));
+  return wg_max_d(h, red);
+}
+
+// ADMM iterations of one instance at fixed rho on one workgroup.  Returns 1
+// solved, 2 max_iter, 3 numerical, 4 rho change (new rho in *rho_new), 6 the
+// iteration count reached park_at with none of these (the instance is handed
+// to a gang of workgroups; its state is complete in global memory).
 // it0: iteration count when this attempt (cold or warm start) began; the rho
 // rule runs every sigma iterations of the attempt.
 __device__ __attribute__((noinline)) int batch_iterate(const BInst* __restrict__ Ip,
                                                        const BatchArgs* __restrict__ ag, double rho, int it0,
-                                                       int max_iter, int* it, double* rho_new, double* rp_out,
-                                                       double* rd_out, LDS char* base) {
+                                                       int max_iter, int park_at, int* it, double* rho_new,
+                                                       double* rp_out, double* rd_out, LDS char* base) {
   Ip = uniform_ptr(Ip);
   ag = uniform_ptr(ag);
   const BInst& I = *Ip;
@@ -687,110 +791,658 @@ __device__ __attribute__((noinline)) int batch_iterate(const BInst* __restrict__
   double* ys = a.dp + I.oy;
   const int t = tid();
   if (a.prof && t < 16) V.pc[t] = 0ull;
-  double hnorm = 0.0;
-  for (int e = t; e < (N + 1) * nx; e += kWG) hnorm = fmax(hnorm, fabs((double)fp[I.oq + e]));
-  for (int e = t; e < N * nu; e += kWG) hnorm = fmax(hnorm, fabs((double)fp[I.orr + e]));
-  hnorm = wg_max_d(hnorm, V.red);
+  const double hnorm = batch_hnorm(I, fp, V.red);
   bool first = true;
   while (true) {
     ++*it;
-    const bool full = first;
+    const bool full = first || (a.refresh > 0 && *it % a.refresh == 0);
     const bool sigma_it = a.adaptive && ((*it - it0) % a.sigma == 0) && *it < max_iter;
-    if (I.box) {
-      batch_backward<true>(Ip, ag, (float)rho, full, base);
-      batch_forward<true>(Ip, ag, rho, full, sigma_it, base);
-    } else {
-      batch_backward<false>(Ip, ag, (float)rho, full, base);
-      batch_forward<false>(Ip, ag, rho, full, sigma_it, base);
-    }
+    if (I.box) batch_backward<true>(Ip, ag, (float)rho, full, base, 0, N, false);
+    else batch_backward<false>(Ip, ag, (float)rho, full, base, 0, N, false);
+    // forward entry x_0 (the backward pass uses V.xz as scratch)
+    for (int j = t; j < nx; j += kWG) V.xz[j] = full ? fp[I.ox0 + j] : 0.f;
+    if (I.box) batch_forward<true>(Ip, ag, rho, full, sigma_it, base, 0, N, false);
+    else batch_forward<false>(Ip, ag, rho, full, sigma_it, base, 0, N, false);
     first = false;
     LDS double* out = V.red + kWG;
-    const double rp = out[0], rd = out[1];
+    double o[6];
+    for (int q = 0; q < 6; ++q) o[q] = out[q];
     lds_barrier();
-    *rp_out = rp;
-    *rd_out = rd;
+    *rp_out = o[0];
+    *rd_out = o[1];
     if (a.prof && t < 16) { atomicAdd(a.prof + t, V.pc[t]); V.pc[t] = 0ull; }
-    if (rp != rp || rd != rd || isinf(rp) || isinf(rd)) return 3;
-    if (rp <= a.tol && rd <= a.tol) return 1;
-    if (*it >= max_iter) return 2;
-    if (sigma_it) {
-      const double vmax = out[2], zmax = out[3], hx = out[4], gl = out[5];
-      const double ps = fmax(vmax, zmax), ds = fmax(fmax(hx, gl), hnorm);
-      const double ratio = (rp / (ps + 1e-10)) / (rd / (ds + 1e-10) + 1e-10);
-      double rn = fmin(fmax(rho * sqrt(ratio), a.rho_min), a.rho_max);
-      if (rn > rho * a.rho_tol || rn < rho / a.rho_tol) {
-        const double f = rho / rn;
-        for (int r = t; r < I.m; r += kWG) ys[r] *= f;
-        __syncthreads();   // cross-thread global update: full fence
-        *rho_new = rn;
-        return 4;
-      }
+    double rn = rho;
+    const int st = admm_decide(a, rho, *it, max_iter, sigma_it, hnorm, o, &rn);
+    if (st == 4) {
+      const double f = rho / rn;
+      for (int r = t; r < I.m; r += kWG) ys[r] *= f;
+      __syncthreads();   // cross-thread global update: full fence
+      *rho_new = rn;
+      return 4;
     }
+    if (st) return st;
+    if (*it >= park_at) return 6;
   }
 }
 
+// ----------------------------------------------------------------- gangs
+// An instance that has not converged within its solo budget (park_at
+// iterations, a function of its size only) is continued by a gang of G
+// workgroups that split its horizon into G chunks (Sec. IV-A: the affine maps
+// of the backward and forward recurrences are composed by associative scans
+// over the horizon).  Per iteration each member
+//   1. folds its chunk's backward recurrence from a zero entry,
+//   2. combines the chunk results across the gang by recursive doubling with
+//      the cached chunk transfer maps Phi[d][r] = Abar_{e-1} ... Abar_s over
+//      2^d chunks (p_s = Phi^T p_e + fold),
+//   3. re-runs its chunk from the exact entry p_e (feed-forward gains k),
+//   4.-6. the same for the forward recurrence (x_e = Phi x_s + fold), the
+//      re-run doing the projection, dual update and residual terms,
+//   7. exchanges the residual terms; every member takes the same decision.
+// The chunk ending at N needs no backward fold (its entry is the terminal
+// value) and the chunk starting at 0 no forward fold.  A rho change runs the
+// factor epoch on member 0 (the others wait), then the transfer maps again.
+// Members exchange through packed (payload, stamp) words; every wait is
+// bounded and a failed wait raises the launch's abort flag.
+
+struct GangLayout {
+  int nlev;
+  size_t bwd, fwd, res, mflag, eword, words;   // 64-bit word offsets
+};
+__host__ __device__ inline int gang_levels(int G) {
+  int l = 0;
+  while ((1 << l) < G) ++l;
+  return l;
+}
+__host__ __device__ inline GangLayout gang_layout(int nx, int G) {
+  GangLayout L;
+  L.nlev = gang_levels(G);
+  size_t o = 0;
+  L.bwd = o; o += (size_t)(L.nlev + 1) * G * nx;
+  L.fwd = o; o += (size_t)(L.nlev + 1) * G * nx;
+  L.res = o; o += (size_t)G * 12;
+  L.mflag = o; o += (size_t)(L.nlev > 0 ? L.nlev : 1) * G;
+  L.eword = o; o += 1;
+  L.words = o;
+  return L;
+}
+// Transfer maps of one instance: [nlev][G][nx][nx] floats.
+__host__ __device__ inline size_t gang_map_floats(int nx, int G) {
+  const int nl = gang_levels(G);
+  return (size_t)(nl > 0 ? nl : 1) * G * nx * nx;
+}
+
+// Control state of an instance handed from its solo workgroup to a gang.
+struct BPark {
+  int it, nupd, nfact, it0, limit, warm, budgeted, restarted;
+  double rho;
+  long long te, ti;
+};
+
+// Device-wide counters of one launch (cleared by the prologue kernel).
+struct BSync {
+  unsigned counter;     // solo work queue
+  unsigned ticket;      // gang tickets
+  unsigned cont;        // instances handed to gangs (slots reserved)
+  unsigned done;        // solo items finished (solved or handed over)
+  int abort;            // a bounded wait gave up
+};
+
+__device__ inline void g_publish(unsigned long long* w, uint32_t stamp, const LDS float* v, int n) {
+  for (int j = tid(); j < n; j += kWG) ll_put(w + j, stamp, __float_as_uint(v[j]));
+}
+// Reads n stamped values into v (all threads call); false (uniformly) if a
+// wait gave up, after raising the abort flag.
+__device__ inline bool g_fetch(const unsigned long long* w, uint32_t stamp, LDS float* v, int n, int* abort,
+                               int* flag) {
+  bool ok = true;
+  for (int j = tid(); j < n; j += kWG) {
+    uint32_t b = 0;
+    if (!ll_get(w + j, stamp, &b, abort)) ok = false;
+    v[j] = __uint_as_float(b);
+  }
+  if (!ok) {
+    *flag = 1;
+    __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  const bool r = *flag == 0;
+  __syncthreads();
+  return r;
+}
+// One stamped word waited for by thread 0 and broadcast (payload in *bits).
+__device__ inline bool g_wait_word(const unsigned long long* w, uint32_t stamp, uint32_t* bits, int* abort,
+                                   int* flag, uint32_t* sbits) {
+  if (tid() == 0) {
+    uint32_t b = 0;
+    if (!ll_get(w, stamp, &b, abort)) {
+      *flag = 1;
+      __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    *sbits = b;
+  }
+  __syncthreads();
+  const bool r = *flag == 0;
+  *bits = *sbits;
+  __syncthreads();
+  return r;
+}
+
+// Chunk [s, e) of member r of G over a horizon of N stages.
+__host__ __device__ inline int gang_cbeg(int r, int N, int G) { return (int)(((long long)r * N) / G); }
+
+// Transfer maps of member r after a factor epoch: Phi[0][r] = product of
+// Abar over its chunk (later stages on the left), Phi[d][r] =
+// Phi[d-1][r + 2^(d-1)] Phi[d-1][r] for r + 2^d <= G.  Each map is published
+// (flag word mflag[d][r], stamp) after it is stored.
+__device__ __attribute__((noinline)) bool gang_maps(const BInst* __restrict__ Ip, const BatchArgs* __restrict__ ag,
+                                                    int r, int G, uint32_t stamp, LDS char* base, int* flag,
+                                                    uint32_t* sbits) {
+  Ip = uniform_ptr(Ip);
+  ag = uniform_ptr(ag);
+  r = uniform_int(r);
+  G = uniform_int(G);
+  const BInst& I = *Ip;
+  const BatchArgs& a = *ag;
+  const int N = I.N, nx = I.nx, nu = I.nu, nc = I.nc, nf = I.nf;
+  const BLayout lay = batch_layout(nx, nu, I.box ? 0 : (nc > nf ? nc : nf));
+  const PkLayout pk = pk_layout(nx, nu);
+  const GangLayout gl = gang_layout(nx, G);
+  LDS float* F0 = (LDS float*)base;
+  LDS float* Pm = F0 + lay.P;    // running product (ld ldP)
+  LDS float* Am = F0 + lay.AB;   // multiplier (ld ldAB)
+  LDS float* Wm = F0 + lay.W;    // product (ld ldW)
+  const int ldP = lay.ldP, ldA = lay.ldAB, ldW = lay.ldW;
+  const float* pkt = a.fp + I.oPk;
+  float* maps = a.gmaps + I.ogm;
+  unsigned long long* words = a.gwords + I.ogw;
+  const size_t xx = (size_t)nx * nx;
+  const int s = gang_cbeg(r, N, G), e = gang_cbeg(r + 1, N, G);
+  for (int i = s; i < e; ++i) {
+    const float* Fi = pkt + (size_t)i * pk.stride + pk.F;
+    LDS float* dst = (i == s) ? Pm : Am;
+    const int ldd = (i == s) ? ldP : ldA;
+    for (int q = wave(); q < nx; q += 4)
+      for (int c = lane(); c < nx; c += 64) dst[q * ldd + c] = Fi[q * pk.ldF + c];
+    __syncthreads();
+    if (i > s) {
+      wg_mm_f32(nx, nx, nx, 1.f, Am, ldA, false, Pm, ldP, false, 0.f, Wm, ldW);
+      for (int q = wave(); q < nx; q += 4)
+        for (int c = lane(); c < nx; c += 64) Pm[q * ldP + c] = Wm[q * ldW + c];
+      __syncthreads();
+    }
+  }
+  for (int d = 0; d < gl.nlev; ++d) {
+    if (r + (1 << d) > G) break;
+    if (d > 0) {
+      const int pr = r + (1 << (d - 1));
+      uint32_t bits;
+      if (!g_wait_word(words + gl.mflag + (size_t)(d - 1) * G + pr, stamp, &bits, &a.sync->abort, flag, sbits))
+        return false;
+      __threadfence();
+      const float* src = maps + ((size_t)(d - 1) * G + pr) * xx;
+      for (int q = wave(); q < nx; q += 4)
+        for (int c = lane(); c < nx; c += 64) Am[q * ldA + c] = src[(size_t)q * nx + c];
+      __syncthreads();
+      wg_mm_f32(nx, nx, nx, 1.f, Am, ldA, false, Pm, ldP, false, 0.f, Wm, ldW);
+      for (int q = wave(); q < nx; q += 4)
+        for (int c = lane(); c < nx; c += 64) Pm[q * ldP + c] = Wm[q * ldW + c];
+      __syncthreads();
+    }
+    float* dstg = maps + ((size_t)d * G + r) * xx;
+    for (int q = wave(); q < nx; q += 4)
+      for (int c = lane(); c < nx; c += 64) dstg[(size_t)q * nx + c] = Pm[q * ldP + c];
+    __threadfence();
+    __syncthreads();
+    if (tid() == 0) ll_put(words + gl.mflag + (size_t)d * G + r, stamp, 1u);
+  }
+  // the forward combination of level d reads Phi[d][r - 2^d + 1], a map of
+  // another member: wait until each of those is stored
+  for (int d = 1; d < gl.nlev; ++d) {
+    const int q = r - (1 << d) + 1;
+    if (q < 1) break;
+    uint32_t bits;
+    if (!g_wait_word(words + gl.mflag + (size_t)d * G + q, stamp, &bits, &a.sync->abort, flag, sbits))
+      return false;
+  }
+  __threadfence();
+  return true;
+}
+
+// One gang member's part of an instance's continuation.
+template <bool BOX>
+__device__ __attribute__((noinline)) void gang_run(const BInst* __restrict__ Ip, const BatchArgs* __restrict__ ag,
+                                                   int idx, int r, int G, LDS char* base) {
+  Ip = uniform_ptr(Ip);
+  ag = uniform_ptr(ag);
+  idx = uniform_int(idx);
+  r = uniform_int(r);
+  G = uniform_int(G);
+  const BInst& I = *Ip;
+  const BatchArgs& a = *ag;
+  const int N = I.N, nx = I.nx, nu = I.nu, nc = I.nc, nf = I.nf;
+  const BLayout lay = batch_layout(nx, nu, BOX ? 0 : (nc > nf ? nc : nf));
+  const IterVecs V = iter_vecs(lay, base);
+  const GangLayout gl = gang_layout(nx, G);
+  const int nlev = gl.nlev;
+  unsigned long long* words = a.gwords + I.ogw;
+  const float* maps = a.gmaps + I.ogm;
+  const size_t xx = (size_t)nx * nx;
+  const int s = gang_cbeg(r, N, G), e = gang_cbeg(r + 1, N, G);
+  const int row0 = s * nc, row1 = e * nc + (e == N ? nf : 0);   // rows owned by this member
+  double* ys = a.dp + I.oy;
+  double* zs = a.dp + I.oz;
+  const int t = tid();
+  __shared__ int s_flag;
+  __shared__ uint32_t s_bits;
+  if (t == 0) s_flag = 0;
+  // clear this member's exchange words, then join
+  for (int d = 0; d <= nlev; ++d)
+    for (int j = t; j < nx; j += kWG) {
+      words[gl.bwd + ((size_t)d * G + r) * nx + j] = 0ull;
+      words[gl.fwd + ((size_t)d * G + r) * nx + j] = 0ull;
+    }
+  for (int j = t; j < 12; j += kWG) words[gl.res + (size_t)r * 12 + j] = 0ull;
+  for (int d = t; d < (nlev > 0 ? nlev : 1); d += kWG) words[gl.mflag + (size_t)d * G + r] = 0ull;
+  if (r == 0 && t == 0) words[gl.eword] = 0ull;
+  __threadfence();
+  __syncthreads();
+  if (t == 0) {
+    atomicAdd(a.join + idx, 1u);
+    unsigned n = 0;
+    while (__hip_atomic_load(a.join + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)G) {
+      if (++n > kSpinLimit || __hip_atomic_load(&a.sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        s_flag = 1;
+        __hip_atomic_store(&a.sync->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  __syncthreads();
+  __threadfence();
+  BPark pkd = a.park[idx];
+  int it = pkd.it, nupd = pkd.nupd, nfact = pkd.nfact, it0 = pkd.it0, limit = pkd.limit;
+  bool warm = pkd.warm != 0, restarted = pkd.restarted != 0;
+  const bool budgeted = pkd.budgeted != 0;
+  double rho = pkd.rho;
+  long long te = pkd.te, ti = pkd.ti;
+  int st = 5;
+  double rp = 0.0, rd = 0.0;
+  bool ok = s_flag == 0;
+  const double hnorm = batch_hnorm(I, a.fp, V.red);
+  if (ok) ok = gang_maps(Ip, ag, r, G, (uint32_t)nfact, base, &s_flag, &s_bits);
+  bool first = false;
+  long long tc = wall_clock64();
+  while (ok) {
+    ++it;
+    const uint32_t stamp = (uint32_t)it;
+    const bool full = first || (a.refresh > 0 && it % a.refresh == 0);
+    const float cst = full ? 1.f : 0.f;
+    const bool sigma_it = a.adaptive && ((it - it0) % a.sigma == 0) && it < limit;
+    // ---- backward: fold, doubling, re-run from the exact entry
+    if (r == G - 1) {
+      batch_backward<BOX>(Ip, ag, (float)rho, full, base, s, e, false);
+    } else if (r > 0) {
+      batch_backward<BOX>(Ip, ag, (float)rho, full, base, s, e, true);
+    }
+    if (r > 0) {
+      g_publish(words + gl.bwd + (size_t)r * nx, stamp, V.g, nx);
+      for (int d = 0; d < nlev; ++d) {
+        const int pr = r + (1 << d);
+        if (pr < G) {
+          if (!g_fetch(words + gl.bwd + ((size_t)d * G + pr) * nx, stamp, V.g2, nx, &a.sync->abort, &s_flag)) {
+            ok = false; break;
+          }
+          lite_gemv_t(nx, nx, maps + ((size_t)d * G + r) * xx, nx, V.g2, V.tv, V.part);
+          for (int j = t; j < nx; j += kWG) V.g[j] += V.tv[j];
+          lds_barrier();
+        }
+        g_publish(words + gl.bwd + ((size_t)(d + 1) * G + r) * nx, stamp, V.g, nx);
+      }
+      if (!ok) break;
+    }
+    if (r < G - 1) {
+      if (!g_fetch(words + gl.bwd + ((size_t)nlev * G + r + 1) * nx, stamp, V.g, nx, &a.sync->abort, &s_flag)) {
+        ok = false; break;
+      }
+      batch_backward<BOX>(Ip, ag, (float)rho, full, base, s, e, false);
+    }
+    // ---- forward: fold, doubling, re-run with projection and residuals
+    for (int j = t; j < nx; j += kWG) V.xz[j] = (r == 0) ? cst * a.fp[I.ox0 + j] : 0.f;
+    if (r == 0) {
+      batch_forward<BOX>(Ip, ag, rho, full, sigma_it, base, s, e, false);
+    } else if (r < G - 1) {
+      batch_forward<BOX>(Ip, ag, rho, full, sigma_it, base, s, e, true);
+    }
+    if (r < G - 1) {
+      for (int j = t; j < nx; j += kWG) V.g[j] = V.xz[j];
+      lds_barrier();
+      g_publish(words + gl.fwd + (size_t)r * nx, stamp, V.g, nx);
+      for (int d = 0; d < nlev; ++d) {
+        const int pr = r - (1 << d);
+        if (pr >= 0) {
+          if (!g_fetch(words + gl.fwd + ((size_t)d * G + pr) * nx, stamp, V.g2, nx, &a.sync->abort, &s_flag)) {
+            ok = false; break;
+          }
+          lite_gemv_n(nx, nx, maps + ((size_t)d * G + pr + 1) * xx, nx, V.g2, V.g, V.part, true);
+        }
+        g_publish(words + gl.fwd + ((size_t)(d + 1) * G + r) * nx, stamp, V.g, nx);
+      }
+      if (!ok) break;
+    }
+    if (r > 0) {
+      if (!g_fetch(words + gl.fwd + ((size_t)nlev * G + r - 1) * nx, stamp, V.xz, nx, &a.sync->abort, &s_flag)) {
+        ok = false; break;
+      }
+      batch_forward<BOX>(Ip, ag, rho, full, sigma_it, base, s, e, false);
+    }
+    first = false;
+    // ---- residual terms of the whole instance (same order on every member)
+    LDS double* out = V.red + kWG;
+    if (t < 6) {
+      const unsigned long long b = (unsigned long long)__double_as_longlong(out[t]);
+      ll_put(words + gl.res + (size_t)r * 12 + 2 * t, stamp, (uint32_t)b);
+      ll_put(words + gl.res + (size_t)r * 12 + 2 * t + 1, stamp, (uint32_t)(b >> 32));
+    }
+    double o[6] = {0, 0, 0, 0, 0, 0};
+    {
+      bool good = true;
+      double mine = 0.0;
+      if (t < 6 * G) {
+        const int q = t % 6, mr = t / 6;
+        uint32_t b[2] = {0, 0};
+        const unsigned long long* w0 = words + gl.res + (size_t)mr * 12 + 2 * q;
+        good = ll_get_batch<2>([&](int k) { return w0 + k; }, 2, stamp, b, &a.sync->abort);
+        mine = __longlong_as_double((long long)(((unsigned long long)b[1] << 32) | b[0]));
+      }
+      if (!good) {
+        s_flag = 1;
+        __hip_atomic_store(&a.sync->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      lds_barrier();
+      if (t < 6 * G) V.red[t] = mine;   // V.red holds kWG + 8 doubles; 6 G <= kWG
+      __syncthreads();
+      if (s_flag) { ok = false; break; }
+      for (int mr = 0; mr < G; ++mr)
+        for (int q = 0; q < 6; ++q) {
+          const double v = V.red[mr * 6 + q];
+          o[q] = (v > o[q] || v != v) ? v : o[q];
+        }
+      __syncthreads();
+    }
+    rp = o[0];
+    rd = o[1];
+    double rn = rho;
+    const int dec = admm_decide(a, rho, it, limit, sigma_it, hnorm, o, &rn);
+    bool epoch = false;
+    if (dec == 4) {
+      const double f = rho / rn;
+      for (int q = row0 + t; q < row1; q += kWG) ys[q] *= f;
+      rho = rn;
+      ++nupd;
+      epoch = true;
+    } else if (warm && budgeted && (dec == 2 || dec == 3)) {
+      // the warm start did not pay off: restart from z = y = 0
+      warm = false;
+      restarted = true;
+      it0 = it;
+      limit = it + a.max_iter;
+      rho = a.rho_cold;
+      for (int q = row0 + t; q < row1; q += kWG) { zs[q] = 0.0; ys[q] = 0.0; }
+      epoch = true;
+    } else if (dec != 0) {
+      st = dec;
+      break;
+    }
+    if (epoch) {
+      __syncthreads();
+      ++nfact;
+      const long long c0 = wall_clock64();
+      ti += c0 - tc;
+      uint32_t bits = 1;
+      if (r == 0) {
+        const bool pd = batch_epoch(Ip, ag, rho, base);
+        __threadfence();
+        __syncthreads();
+        if (t == 0) ll_put(words + gl.eword, (uint32_t)nfact, pd ? 1u : 2u);
+        bits = pd ? 1u : 2u;
+      } else {
+        if (!g_wait_word(words + gl.eword, (uint32_t)nfact, &bits, &a.sync->abort, &s_flag, &s_bits)) {
+          ok = false; break;
+        }
+        __threadfence();
+      }
+      if (bits != 1u) { st = -1; break; }
+      if (!gang_maps(Ip, ag, r, G, (uint32_t)nfact, base, &s_flag, &s_bits)) { ok = false; break; }
+      tc = wall_clock64();
+      te += tc - c0;
+      first = true;
+    }
+  }
+  ti += wall_clock64() - tc;
+  if (!ok) st = 5;
+  if (r == 0 && t == 0) {
+    BResult res;
+    res.status = st; res.iterations = it; res.rho_updates = nupd; res.factorizations = nfact;
+    res.restarted = restarted ? 1 : 0;
+    res.r_p = rp; res.r_d = rd; res.rho = rho;
+    res.t_epoch = te; res.t_iter = ti;
+    a.res[idx] = res;
+  }
+  __syncthreads();
+}
+
+// Solo part of one instance on this workgroup (cold or warm start, epochs,
+// iterations); hands the instance over to a gang when its iteration count
+// reaches park_at.
+__device__ __attribute__((noinline)) void batch_solo(const BatchArgs* __restrict__ ag, int idx, LDS char* base) {
+  ag = uniform_ptr(ag);
+  idx = uniform_int(idx);
+  const BatchArgs& a = *ag;
+  BSync* sy = a.sync;
+  const BInst* Ip = a.inst + idx;
+  const int m = Ip->m;
+  const long long oz = Ip->oz, oy = Ip->oy;
+  bool warm = a.warm[idx] != 0;
+  if (!warm)
+    for (int r = tid(); r < m; r += kWG) { a.dp[oz + r] = 0.0; a.dp[oy + r] = 0.0; }
+  __syncthreads();
+  double rho = a.rho0[idx];
+  int it = 0, nupd = 0, nfact = 0, st = 0, restarted = 0;
+  double rp = 0.0, rd = 0.0;
+  const bool budgeted = warm && a.warm_budget > 0 && a.warm_budget < a.max_iter;
+  int limit = budgeted ? a.warm_budget : a.max_iter, it0 = 0;
+  const int park_at = a.gang > 1 ? Ip->park_at : 0x7fffffff;
+  long long te = 0, ti = 0;
+  while (true) {
+    ++nfact;
+    const long long c0 = wall_clock64();
+    if (!batch_epoch(Ip, ag, rho, base)) { st = -1; break; }
+    const long long c1 = wall_clock64();
+    double rn = rho;
+    st = batch_iterate(Ip, ag, rho, it0, limit, park_at, &it, &rn, &rp, &rd, base);
+    te += c1 - c0;
+    ti += wall_clock64() - c1;
+    if (st == 4) { rho = rn; ++nupd; continue; }
+    if (warm && budgeted && (st == 2 || st == 3)) {
+      // the warm start did not pay off: restart from z = y = 0 with a
+      // full iteration budget of its own
+      warm = false;
+      restarted = 1;
+      it0 = it;
+      limit = it + a.max_iter;
+      rho = a.rho_cold;
+      for (int r = tid(); r < m; r += kWG) { a.dp[oz + r] = 0.0; a.dp[oy + r] = 0.0; }
+      __syncthreads();
+      continue;
+    }
+    break;
+  }
+  if (st == 6) {
+    // hand over: state to global memory, then the slot (release)
+    __syncthreads();
+    if (tid() == 0) {
+      BPark pk;
+      pk.it = it; pk.nupd = nupd; pk.nfact = nfact; pk.it0 = it0; pk.limit = limit;
+      pk.warm = warm ? 1 : 0; pk.budgeted = budgeted ? 1 : 0; pk.restarted = restarted;
+      pk.rho = rho; pk.te = te; pk.ti = ti;
+      a.park[idx] = pk;
+      __threadfence();
+      const unsigned slot = atomicAdd(&sy->cont, 1u);
+      atomicExch(a.cont_list + slot, idx);
+    }
+  } else if (tid() == 0) {
+    BResult r;
+    r.status = st; r.iterations = it; r.rho_updates = nupd; r.factorizations = nfact;
+    r.restarted = restarted;
+    r.r_p = rp; r.r_d = rd; r.rho = rho;
+    r.t_epoch = te; r.t_iter = ti;
+    r.r_dyn = 0.0;
+    a.res[idx] = r;
+  }
+  if (tid() == 0) {
+    __threadfence();
+    atomicAdd(&sy->done, 1u);
+  }
+  __syncthreads();
+}
+
+// Persistent batched solver.  A free workgroup first joins a gang whose
+// instance has been handed over and still lacks members (so a handed-over
+// instance waits only for the solo items running when it was handed over),
+// else takes the next solo instance from the work queue (largest first),
+// else waits for hand-overs until every solo item has finished.  Gang tickets
+// are consecutive per handed-over instance (G per instance, in hand-over
+// order); a ticket is taken only for an instance already handed over while
+// solo items remain, so no workgroup waits on an instance that may never
+// come while runnable work is queued.  A gang is complete before any later
+// ticket is taken, hence a gang waits only for workgroups busy elsewhere
+// (G <= grid).
 __global__ void __launch_bounds__(kWG) k_batch(const BatchArgs* __restrict__ ag) {
   extern __shared__ __align__(16) char lds_generic[];
   LDS char* base = (LDS char*)lds_generic;
-  __shared__ unsigned s_item;
+  __shared__ int s_code;
   const BatchArgs& a = *ag;
+  BSync* sy = a.sync;
+  const int G = a.gang > 1 ? a.gang : 1;
+  const unsigned count = (unsigned)a.count;
   while (true) {
-    if (tid() == 0) s_item = atomicAdd(a.counter, 1u);
-    __syncthreads();
-    const unsigned item = s_item;
-    __syncthreads();
-    if (item >= (unsigned)a.count) break;
-    const int idx = a.order[item];
-    const BInst* Ip = a.inst + idx;
-    const int m = Ip->m;
-    const long long oz = Ip->oz, oy = Ip->oy;
-    bool warm = a.warm[idx] != 0;
-    if (!warm)
-      for (int r = tid(); r < m; r += kWG) { a.dp[oz + r] = 0.0; a.dp[oy + r] = 0.0; }
-    __syncthreads();
-    double rho = a.rho0[idx];
-    int it = 0, nupd = 0, nfact = 0, st = 0, restarted = 0;
-    double rp = 0.0, rd = 0.0;
-    const bool budgeted = warm && a.warm_budget > 0 && a.warm_budget < a.max_iter;
-    int limit = budgeted ? a.warm_budget : a.max_iter, it0 = 0;
-    long long te = 0, ti = 0;
-    while (true) {
-      ++nfact;
-      const long long c0 = wall_clock64();
-      if (!batch_epoch(Ip, ag, rho, base)) { st = -1; break; }
-      const long long c1 = wall_clock64();
-      double rn = rho;
-      st = batch_iterate(Ip, ag, rho, it0, limit, &it, &rn, &rp, &rd, base);
-      te += c1 - c0;
-      ti += wall_clock64() - c1;
-      if (st == 4) { rho = rn; ++nupd; continue; }
-      if (warm && budgeted && (st == 2 || st == 3)) {
-        // the warm start did not pay off: restart from z = y = 0 with a
-        // full iteration budget of its own
-        warm = false;
-        restarted = 1;
-        it0 = it;
-        limit = it + a.max_iter;
-        rho = a.rho_cold;
-        for (int r = tid(); r < m; r += kWG) { a.dp[oz + r] = 0.0; a.dp[oy + r] = 0.0; }
-        __syncthreads();
-        continue;
-      }
-      break;
-    }
+    // code >= 0: gang member (instance << 8 | rank); -1 - item: solo item; -1 - count: exit
     if (tid() == 0) {
-      BResult r;
-      r.status = st; r.iterations = it; r.rho_updates = nupd; r.factorizations = nfact;
-      r.restarted = restarted;
-      r.r_p = rp; r.r_d = rd; r.rho = rho;
-      r.t_epoch = te; r.t_iter = ti;
-      a.res[idx] = r;
+      int code = -1 - (int)count;
+      bool decided = false;
+      if (G > 1) {
+        // 1. an open seat in a handed-over instance's gang
+        unsigned tk = __hip_atomic_load(&sy->ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (true) {
+          const unsigned cn = __hip_atomic_load(&sy->cont, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (tk >= cn * (unsigned)G) break;
+          if (__hip_atomic_compare_exchange_strong(&sy->ticket, &tk, tk + 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT)) {
+            const unsigned slot = tk / (unsigned)G;
+            int v = -1;
+            unsigned n = 0;
+            // the slot is reserved: its entry is being written
+            while ((v = __hip_atomic_load(a.cont_list + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < 0 &&
+                   ++n < kSpinLimit)
+              __builtin_amdgcn_s_sleep(1);
+            if (v < 0) __hip_atomic_store(&sy->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else code = (v << 8) | (int)(tk % (unsigned)G);
+            decided = true;
+            break;
+          }
+        }
+      }
+      if (!decided) {
+        // 2. the next solo item
+        const unsigned item = atomicAdd(&sy->counter, 1u);
+        if (item < count) {
+          code = -1 - (int)item;
+          decided = true;
+        }
+      }
+      if (!decided && G > 1) {
+        // 3. no solo work left: wait for the next hand-over, or for the end
+        const unsigned tk = atomicAdd(&sy->ticket, 1u);
+        const unsigned slot = tk / (unsigned)G;
+        if (slot < count) {
+          unsigned n = 0;
+          while (true) {
+            const int v = __hip_atomic_load(a.cont_list + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v >= 0) { code = (v << 8) | (int)(tk % (unsigned)G); break; }
+            const unsigned dn = __hip_atomic_load(&sy->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            const unsigned cn = __hip_atomic_load(&sy->cont, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (dn >= count && slot >= cn) break;
+            if (__hip_atomic_load(&sy->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            if (++n > 64u * kSpinLimit) {
+              __hip_atomic_store(&sy->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+          }
+        }
+      }
+      s_code = code;
     }
     __syncthreads();
+    const int code = s_code;
+    __syncthreads();
+    if (code == -1 - (int)count) break;
+    if (code < 0) {
+      batch_solo(ag, a.order[-1 - code], base);
+    } else {
+      __threadfence();
+      const int idx = code >> 8, r = code & 255;
+      const BInst* Ip = a.inst + idx;
+      if (Ip->box) gang_run<true>(Ip, ag, idx, r, G, base);
+      else gang_run<false>(Ip, ag, idx, r, G, base);
+    }
   }
 }
 
-__global__ void k_zero_u32(unsigned* p) { *p = 0u; }
+// Dynamics residual of each instance's returned iterate, one workgroup per
+// instance: max over stages and state rows of |x_{k+1} - A_k x_k - B_k u_k -
+// b_k| in FP64 on the FP32 stage data.
+__global__ void __launch_bounds__(kWG) k_batch_rdyn(const BInst* __restrict__ inst, const float* __restrict__ fp,
+                                                    const double* __restrict__ dp, BResult* res) {
+  __shared__ double red[kWG];
+  const BInst I = inst[blockIdx.x];
+  const int nx = I.nx, nu = I.nu;
+  double m = 0.0;
+  for (int e = tid(); e < I.N * nx; e += kWG) {
+    const int k = e / nx, i = e - k * nx;
+    const float* Ar = fp + I.oA + ((size_t)k * nx + i) * nx;
+    const float* Br = fp + I.oB + ((size_t)k * nx + i) * nu;
+    const double* xk = dp + I.oX + (size_t)k * nx;
+    const double* uk = dp + I.oU + (size_t)k * nu;
+    double v = dp[I.oX + (size_t)(k + 1) * nx + i] - (double)fp[I.ob + (size_t)k * nx + i];
+    for (int j = 0; j < nx; ++j) v -= (double)Ar[j] * xk[j];
+    for (int j = 0; j < nu; ++j) v -= (double)Br[j] * uk[j];
+    const double a = fabs(v);
+    m = (a > m || a != a) ? a : m;
+  }
+  red[tid()] = m;
+  __syncthreads();
+  for (int st = kWG / 2; st > 0; st >>= 1) {
+    if (tid() < st) {
+      const double a = red[tid()], b = red[tid() + st];
+      red[tid()] = (b > a || b != b) ? b : a;
+    }
+    __syncthreads();
+  }
+  if (tid() == 0) res[blockIdx.x].r_dyn = red[0];
+}
+
+// Clears the launch's counters, the hand-over list and the gang join counters.
+__global__ void k_batch_prologue(BSync* sync, int* cont_list, unsigned* join, int count) {
+  const int i = blockIdx.x * blockDim.x + tid();
+  if (i == 0) {
+    sync->counter = 0u; sync->ticket = 0u; sync->cont = 0u; sync->done = 0u; sync->abort = 0;
+  }
+  if (i < count) { cont_list[i] = -1; join[i] = 0u; }
+}
 
 // ------------------------------------------------------------------ host
 static bool is_box(const gsls_qp_desc& d, const std::vector<double>& C, const std::vector<double>& D,
@@ -900,8 +1552,11 @@ int batch_setup(const gsls_qp_desc* descs, int count, const gsls_settings* s, hi
   if (hipMalloc(&B->d_rho, count * sizeof(double)) != hipSuccess) return GSLS_ERR_OOM;
   if (hipMalloc(&B->d_warm, count * sizeof(int)) != hipSuccess) return GSLS_ERR_OOM;
   if (hipMalloc(&B->d_res, count * sizeof(BResult)) != hipSuccess) return GSLS_ERR_OOM;
-  if (hipMalloc(&B->d_counter, sizeof(unsigned)) != hipSuccess) return GSLS_ERR_OOM;
   if (hipMalloc(&B->d_args, sizeof(BatchArgs)) != hipSuccess) return GSLS_ERR_OOM;
+  if (hipMalloc(&B->d_sync, sizeof(BSync)) != hipSuccess) return GSLS_ERR_OOM;
+  if (hipMalloc(&B->d_cont, count * sizeof(int)) != hipSuccess) return GSLS_ERR_OOM;
+  if (hipMalloc(&B->d_join, count * sizeof(unsigned)) != hipSuccess) return GSLS_ERR_OOM;
+  if (hipMalloc(&B->d_park, count * sizeof(BPark)) != hipSuccess) return GSLS_ERR_OOM;
   if (hipMemcpy(B->fp, fpool.data(), B->nfp * 4, hipMemcpyHostToDevice) != hipSuccess) return GSLS_ERR_HIP;
   if (hipMemcpy(B->dp, dpool.data(), B->ndp * 8, hipMemcpyHostToDevice) != hipSuccess) return GSLS_ERR_HIP;
   if (hipMemcpy(B->d_inst, B->inst.data(), count * sizeof(BInst), hipMemcpyHostToDevice) != hipSuccess)
@@ -914,8 +1569,9 @@ int batch_setup(const gsls_qp_desc* descs, int count, const gsls_settings* s, hi
   if (hipGetDevice(&dev) != hipSuccess) return GSLS_ERR_HIP;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return GSLS_ERR_HIP;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_batch, kWG, lds) != hipSuccess) per = 1;
-  B->grid = std::min(count, cus * std::max(per, 1));
+  B->grid = cus * std::max(per, 1);
   if (hipEventCreate(&B->e0) != hipSuccess || hipEventCreate(&B->e1) != hipSuccess) return GSLS_ERR_HIP;
+  if (int rc = batch_set_schedule(B, 0, 0.0)) return rc;
   B->row_off.assign(count + 1, 0);
   for (int c = 0; c < count; ++c) B->row_off[c + 1] = B->row_off[c] + B->inst[c].N + 1;
   const int rows = B->row_off[count];
@@ -928,6 +1584,54 @@ int batch_setup(const gsls_qp_desc* descs, int count, const gsls_settings* s, hi
     return GSLS_ERR_HIP;
   if (hipMemcpy(B->d_row_off, B->row_off.data(), (count + 1) * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
     return GSLS_ERR_HIP;
+  return GSLS_OK;
+}
+
+// Solo cost model of one stage of one iteration on one workgroup (us): a
+// fixed latency per stage and direction plus a part growing with the packet
+// (fitted to the per-instance device times of the uneven benchmark batch).
+static double solo_stage_us(int nx, int nu) { return 2.9 + 0.068 * (nx + nu); }
+
+int batch_set_schedule(BatchSolver* B, int gang, double park_share) {
+  if (gang < 0 || gang > kGangMax || !(park_share >= 0.0) || !std::isfinite(park_share)) return GSLS_ERR_INVALID_ARG;
+  if (gang == 0) gang = kGangAuto;
+  if (park_share == 0.0) park_share = kParkShareAuto;
+  gang = std::min(gang, B->grid / 2);
+  if (gang < 2) gang = 1;
+  const int count = B->count;
+  // hand-over points: an instance long enough to split (N >= 2 G) leaves
+  // its solo workgroup once its estimated solo work exceeds park_share times
+  // one workgroup's share of the batch (every instance at 100 iterations)
+  double total = 0.0;
+  for (const BInst& I : B->inst) total += (double)I.N * solo_stage_us(I.nx, I.nu);
+  const double wb = park_share * total * 100.0 / (double)B->grid;
+  size_t nw = 0, nm = 0;
+  for (BInst& I : B->inst) {
+    I.park_at = 0x7fffffff;
+    I.ogw = 0; I.ogm = 0;
+    if (gang > 1 && I.N >= 2 * gang) {
+      const double w = (double)I.N * solo_stage_us(I.nx, I.nu);
+      I.park_at = (int)std::max(10.0, std::ceil(wb / w));
+      I.ogw = (long long)nw; I.ogm = (long long)nm;
+      nw += gang_layout(I.nx, gang).words;
+      nm += (gang_map_floats(I.nx, gang) + 63) & ~(size_t)63;
+    }
+  }
+  if (B->d_gwords) { (void)hipFree(B->d_gwords); B->d_gwords = nullptr; }
+  if (B->d_gmaps) { (void)hipFree(B->d_gmaps); B->d_gmaps = nullptr; }
+  if (nw > 0) {
+    if (hipMalloc(&B->d_gwords, nw * 8) != hipSuccess) return GSLS_ERR_OOM;
+    if (hipMalloc(&B->d_gmaps, nm * 4) != hipSuccess) return GSLS_ERR_OOM;
+  } else {
+    gang = 1;
+  }
+  if (hipMemcpy(B->d_inst, B->inst.data(), count * sizeof(BInst), hipMemcpyHostToDevice) != hipSuccess)
+    return GSLS_ERR_HIP;
+  B->gang = gang;
+  B->park_share = park_share;
+  // the captured launch depends on the schedule
+  if (B->gexec) { (void)hipGraphExecDestroy(B->gexec); B->gexec = nullptr; }
+  if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
   return GSLS_OK;
 }
 
@@ -962,8 +1666,11 @@ int batch_run(BatchSolver* B, double tol, int warm_budget, gsls_result* out, dou
   BatchArgs a{};
   a.inst = B->d_inst; a.order = B->d_order; a.count = count; a.fp = B->fp; a.dp = B->dp; a.rho0 = B->d_rho;
   a.tol = tol; a.max_iter = B->st.max_iter; a.adaptive = B->st.adaptive_rho; a.sigma = B->st.sigma;
+  a.refresh = B->st.refresh;
   a.rho_min = B->st.rho_min; a.rho_max = B->st.rho_max; a.rho_tol = B->st.rho_tol;
-  a.res = B->d_res; a.counter = B->d_counter; a.warm = B->d_warm;
+  a.res = B->d_res; a.warm = B->d_warm;
+  a.gang = B->gang; a.sync = (BSync*)B->d_sync; a.cont_list = B->d_cont; a.join = B->d_join;
+  a.park = (BPark*)B->d_park; a.gwords = B->d_gwords; a.gmaps = B->d_gmaps;
   a.warm_budget = warm_budget; a.rho_cold = 1.0;
   a.prof = B->d_prof;
   if (hipMemcpyAsync(B->d_args, &a, sizeof(a), hipMemcpyHostToDevice, B->stream) != hipSuccess) return GSLS_ERR_HIP;
@@ -976,8 +1683,9 @@ int batch_run(BatchSolver* B, double tol, int warm_budget, gsls_result* out, dou
     hipStream_t cs;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return GSLS_ERR_HIP;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return GSLS_ERR_HIP;
-    k_zero_u32<<<1, 1, 0, cs>>>(B->d_counter);
+    k_batch_prologue<<<(count + 255) / 256, 256, 0, cs>>>((BSync*)B->d_sync, B->d_cont, B->d_join, count);
     k_batch<<<B->grid, kWG, B->lds, cs>>>(B->d_args);
+    k_batch_rdyn<<<count, kWG, 0, cs>>>(B->d_inst, B->fp, B->dp, B->d_res);
     if (hipStreamEndCapture(cs, &B->graph) != hipSuccess) return GSLS_ERR_HIP;
     (void)hipStreamDestroy(cs);
     if (hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0) != hipSuccess) return GSLS_ERR_HIP;
@@ -1000,9 +1708,10 @@ int batch_run(BatchSolver* B, double tol, int warm_budget, gsls_result* out, dou
     gsls_result r{};
     const BResult& b = res[c];
     if (b.status == -1) rc = GSLS_ERR_NOT_PD;
+    if (b.status == 5 && rc == GSLS_OK) rc = GSLS_ERR_HIP;   // a gang's bounded wait gave up
     r.status = b.status == 1 ? GSLS_SOLVED : (b.status == 2 ? GSLS_MAX_ITER : GSLS_NUMERICAL_FAIL);
     r.iterations = b.iterations; r.rho_updates = b.rho_updates; r.factorizations = b.factorizations;
-    r.r_p = b.r_p; r.r_d = b.r_d; r.rho = b.rho; r.ms_total = t;
+    r.r_p = b.r_p; r.r_d = b.r_d; r.rho = b.rho; r.ms_total = t; r.r_dyn = b.r_dyn;
     r.ms_factor = (double)b.t_epoch * 1e-5;    // 100 MHz counter -> ms (this instance's workgroup)
     r.ms_iterate = (double)b.t_iter * 1e-5;
     r.cold_restart = b.restarted;
@@ -1099,6 +1808,20 @@ int gsls_batch_get(gsls_batch* b, int32_t index, double* X, double* U, double* z
 }
 
 void gsls_batch_free(gsls_batch* b) { delete b; }
+
+int gsls_batch_set_schedule(gsls_batch* b, int32_t gang, double park_share) {
+  if (!b) return GSLS_ERR_INVALID_ARG;
+  return gsls::batch_set_schedule(&b->s, gang, park_share);
+}
+
+int gsls_batch_get_schedule(gsls_batch* b, int32_t* gang, double* park_share, int32_t* park_at) {
+  if (!b) return GSLS_ERR_INVALID_ARG;
+  if (gang) *gang = b->s.gang;
+  if (park_share) *park_share = b->s.park_share;
+  if (park_at)
+    for (int c = 0; c < b->s.count; ++c) park_at[c] = b->s.inst[c].park_at;
+  return GSLS_OK;
+}
 
 int gsls_batch_debug_phase_cycles(gsls_batch* b, int32_t enable, double* cycles16) {
   if (!b) return GSLS_ERR_INVALID_ARG;

@@ -11,6 +11,8 @@ namespace gsls {
 
 struct BInst {
   int N, nx, nu, nc, nf, box, m;
+  int park_at;                                             // solo iterations before a gang takes over
+  long long ogw, ogm;                                      // gang exchange words / transfer maps
   long long oA, oB, ob, oQ, oR, oS, oq, orr, oG, oCN, ox0;  // float pool: problem
   long long oPk, okff;                                     // float pool: stage packets, feed-forward k
   long long ol, ou, oz, oy, ov, owp, oX, oU;                // double pool
@@ -20,6 +22,7 @@ struct BResult {
   int status, iterations, rho_updates, factorizations, restarted;
   double r_p, r_d, rho;
   long long t_epoch, t_iter;   // device clock ticks (100 MHz real-time counter)
+  double r_dyn;                // dynamics residual of the returned iterate
 };
 
 struct BatchArgs {
@@ -31,14 +34,22 @@ struct BatchArgs {
   const double* rho0;          // [count]
   double tol;
   int max_iter, adaptive, sigma;
+  int refresh;                 // full evaluation at iteration counts divisible by refresh (0: none)
   double rho_min, rho_max, rho_tol;
   BResult* res;                // [count]
-  unsigned* counter;
   int* warm;                   // [count] 1: start from the given z, y
   int warm_budget;             // > 0: a warm start that has not converged after
                                // this many iterations restarts cold
   double rho_cold;             // rho of such a cold restart
   unsigned long long* prof;    // [16] phase clock counters, or null
+  // gangs (continuation of instances over several workgroups)
+  int gang;                    // workgroups per gang (<= 1: no gangs)
+  struct BSync* sync;          // launch counters (cleared by the prologue)
+  int* cont_list;              // [count] instances handed to gangs, in order
+  unsigned* join;              // [count] gang join counters
+  struct BPark* park;          // [count] control state at hand-over
+  unsigned long long* gwords;  // exchange words (per instance at BInst::ogw)
+  float* gmaps;                // transfer maps (per instance at BInst::ogm)
 };
 
 struct BatchSolver {
@@ -56,9 +67,18 @@ struct BatchSolver {
   double* d_rho = nullptr;
   int* d_warm = nullptr;
   BResult* d_res = nullptr;
-  unsigned* d_counter = nullptr;
   BatchArgs* d_args = nullptr;    // kernel arguments (the graph keeps this pointer)
   int grid = 0;
+  // gang schedule: workgroups per gang and the solo work (as a share of one
+  // workgroup's share of an estimated batch) after which an instance is handed over
+  int gang = 0;
+  double park_share = 0.0;
+  void* d_sync = nullptr;
+  int* d_cont = nullptr;
+  unsigned* d_join = nullptr;
+  void* d_park = nullptr;
+  unsigned long long* d_gwords = nullptr;
+  float* d_gmaps = nullptr;
   // feature rows of the learned warm start: one per stage k = 0..N of every
   // instance, instance c owning rows row_off[c] .. row_off[c+1]-1
   unsigned long long* d_prof = nullptr;   // phase counters when profiling is on
@@ -67,14 +87,14 @@ struct BatchSolver {
   int* d_row_off = nullptr;    // [count + 1]
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  double graph_key[3] = {-1, -1, -1};   // (tol, warm budget, profiling) of the captured graph
+  double graph_key[4] = {-1, -1, -1, -1};   // (tol, warm budget, profiling, schedule) of the captured graph
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ~BatchSolver() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     for (void* p : {(void*)fp, (void*)dp, (void*)d_inst, (void*)d_order, (void*)d_rho, (void*)d_warm,
-                    (void*)d_res, (void*)d_counter, (void*)d_row_inst, (void*)d_row_off, (void*)d_prof,
-                    (void*)d_args})
+                    (void*)d_res, (void*)d_row_inst, (void*)d_row_off, (void*)d_prof, (void*)d_args,
+                    d_sync, (void*)d_cont, (void*)d_join, d_park, (void*)d_gwords, (void*)d_gmaps})
       if (p) (void)hipFree(p);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -91,6 +111,9 @@ int batch_upload_x0(BatchSolver* B, const double* const* x0);
 // Launches the captured solve graph with the start (rho, warm flags, z, y)
 // already in device memory, waits, and fills out / ms.
 int batch_run(BatchSolver* B, double tol, int warm_budget, gsls_result* out, double* ms);
+// Sets the gang schedule (gang <= 1: every instance on one workgroup) and the
+// per-instance hand-over points.
+int batch_set_schedule(BatchSolver* B, int gang, double park_share);
 
 }  // namespace gsls
 

@@ -282,7 +282,8 @@ __global__ void __launch_bounds__(kWG) k_admm(IterArgs<T> a) {
     ++it;
     ++stamp;
     const bool sigma_it = a.ip.adaptive && a.ip.sigma > 0 && (it % a.ip.sigma == 0) && it < a.ip.max_iter;
-    const bool full = first || !kIncremental;   // evaluate the affine map in full
+    // evaluate the affine map in full (FP64; mixed after an epoch and at refresh points)
+    const bool full = first || !kIncremental || (a.ip.refresh > 0 && it % a.ip.refresh == 0);
     const T cst = full ? T(1) : T(0);           // weight of the w-independent terms
     // ---------------------------------------------------- 1. linear terms
     for (int i = s; i < e; ++i) {
@@ -628,6 +629,47 @@ int launch_admm(const IterArgs<T>& args, hipStream_t st) {
   if (e != hipSuccess) return GSLS_ERR_HIP;
   return GSLS_OK;
 }
+
+// Dynamics residual of the FP64 iterate (X, U) against the working-precision
+// stage data: one workgroup per stage, ctl->r_dyn = max over stages and rows
+// of |x_{k+1} - A_k x_k - B_k u_k - b_k| (a max of non-negative doubles, so
+// the maximum of their bit patterns).
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_rdyn(DevProblem<T> pb, const double* X, const double* U, IterCtl* ctl) {
+  __shared__ double red[kWG];
+  const int nx = pb.nx, nu = pb.nu;
+  double m = 0.0;
+  for (int k = blockIdx.x; k < pb.N; k += gridDim.x) {
+    const double* xk = X + (size_t)k * nx;
+    const double* uk = U + (size_t)k * nu;
+    for (int i = tid(); i < nx; i += kWG) {
+      const T* Ar = pb.A + ((size_t)k * nx + i) * nx;
+      const T* Br = pb.B + ((size_t)k * nx + i) * nu;
+      double v = X[(size_t)(k + 1) * nx + i] - (double)pb.b[(size_t)k * nx + i];
+      for (int j = 0; j < nx; ++j) v -= (double)Ar[j] * xk[j];
+      for (int j = 0; j < nu; ++j) v -= (double)Br[j] * uk[j];
+      const double a = fabs(v);
+      m = (a > m || a != a) ? a : m;
+    }
+  }
+  red[tid()] = m;
+  __syncthreads();
+  for (int st = kWG / 2; st > 0; st >>= 1) {
+    if (tid() < st) red[tid()] = nanmax(red[tid()], red[tid() + st]);
+    __syncthreads();
+  }
+  if (tid() == 0)
+    atomicMax((unsigned long long*)&ctl->r_dyn, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+template <typename T>
+int launch_rdyn(const DevProblem<T>& pb, const double* X, const double* U, IterCtl* ctl, hipStream_t st) {
+  if (pb.N < 1) return GSLS_OK;
+  k_rdyn<T><<<std::min(pb.N, 1024), kWG, 0, st>>>(pb, X, U, ctl);
+  return hipGetLastError() == hipSuccess ? GSLS_OK : GSLS_ERR_HIP;
+}
+template int launch_rdyn<float>(const DevProblem<float>&, const double*, const double*, IterCtl*, hipStream_t);
+template int launch_rdyn<double>(const DevProblem<double>&, const double*, const double*, IterCtl*, hipStream_t);
 
 template size_t admm_lds_bytes<float>(int, int, int, int, int, int, bool);
 template size_t admm_lds_bytes<double>(int, int, int, int, int, int, bool);

@@ -16,6 +16,15 @@
 // C[i0 + 4(l/16) + r][j0 + l%16] in accumulator r.  Weight gradients reduce
 // over the rows in K chunks (one partial per chunk, summed in a fixed order:
 // deterministic).
+//
+// Hidden activations are kept as a pair of BF16 arrays, h = hi + lo with
+// hi = bf16(h) and lo = bf16(h - hi) (about 16 significant bits), and every
+// product that consumes them (the next layer's forward GEMM and the weight
+// gradient h^T delta) runs the matrix cores on both halves.  Rounding the
+// activations to a single BF16 moves ReLU decisions downstream and costs a
+// few per cent on the first layer's weight gradient; with the pair the
+// gradients follow the FP64 definition to the BF16 rounding of the weights,
+// inputs and back-propagated deltas (a few 1e-3).  Deltas stay single BF16.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -54,10 +63,12 @@ enum { EPI_BIAS_RELU = 0, EPI_BIAS = 1, EPI_RELU_MASK = 2, EPI_PARTIAL = 3 };
 struct GemmArgs {
   int M, N, K;
   const u16* A; int lda; int ta; const int* ridx;   // ridx: gather of A's stored rows
+  const u16* Alo;                                   // nullable: low BF16 half of A (A = A + Alo)
   const u16* B; int ldb; int tb;
   const float* bias;                                // EPI_BIAS*
   const u16* act; int ldact;                        // EPI_RELU_MASK: mask [act > 0]
   u16* Cb; float* Cf; int ldc;
+  u16* Clo;                                         // EPI_BIAS_RELU, nullable: low half of the output
   int kc;                                           // K chunk per blockIdx.z
 };
 
@@ -102,9 +113,12 @@ __device__ __forceinline__ void stage_tile(LDS u16 (*S)[BKP], const u16* X, int 
 
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g, int epi) {
   __shared__ __align__(16) u16 As_[BM][BKP];
+  __shared__ __align__(16) u16 Al_[BM][BKP];
   __shared__ __align__(16) u16 Bs_[BN][BKP];
   LDS u16 (*As)[BKP] = (LDS u16 (*)[BKP])As_;
+  LDS u16 (*Al)[BKP] = (LDS u16 (*)[BKP])Al_;
   LDS u16 (*Bs)[BKP] = (LDS u16 (*)[BKP])Bs_;
+  const bool split = g.Alo != nullptr;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN, kz = blockIdx.z;
   const int kbeg = kz * g.kc, kend = min(g.K, kbeg + g.kc);
   const int l = lane(), w = wave();
@@ -118,6 +132,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g, int epi) {
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
     // A(m, k): ta -> stored [K][M] (m contiguous); else [M][K]
     stage_tile(As, g.A, g.lda, !g.ta, g.ridx, m0, g.M, k0, kend);
+    if (split) stage_tile(Al, g.Alo, g.lda, !g.ta, g.ridx, m0, g.M, k0, kend);
     // B(k, n): tb -> stored [N][K] (k contiguous); else [K][N]
     stage_tile(Bs, g.B, g.ldb, g.tb, nullptr, n0, g.N, k0, kend);
     __syncthreads();
@@ -130,6 +145,16 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g, int epi) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (split) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        a[i] = __builtin_bit_cast(bf16x8, *(const LDS u16x8*)&Al[wm + i * 16 + r16][q * 8]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
     __syncthreads();
   }
 #pragma unroll
@@ -143,7 +168,10 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g, int epi) {
         float v = acc[i][j][r];
         const long long o = (long long)row * g.ldc + col;
         if (epi == EPI_BIAS_RELU) {
-          g.Cb[o] = f2bf(fmaxf(v + g.bias[col], 0.f));
+          const float h = fmaxf(v + g.bias[col], 0.f);
+          const u16 hi = f2bf(h);
+          g.Cb[o] = hi;
+          if (g.Clo) g.Clo[o] = f2bf(h - bf2f(hi));
         } else if (epi == EPI_BIAS) {
           g.Cf[o] = v + g.bias[col];
         } else if (epi == EPI_RELU_MASK) {
@@ -375,7 +403,8 @@ struct WsModel {
   int step = 0;
   // workspace (grown on demand)
   int cap = 0;
-  u16 *H[3] = {nullptr, nullptr, nullptr}, *dY = nullptr, *dA[2] = {nullptr, nullptr}, *Xw = nullptr;
+  u16 *H[3] = {nullptr, nullptr, nullptr}, *Hl[3] = {nullptr, nullptr, nullptr};   // activations, hi / lo
+  u16 *dY = nullptr, *dA[2] = {nullptr, nullptr}, *Xw = nullptr;
   float *Y = nullptr, *part = nullptr, *lpart = nullptr, *cpart = nullptr;
   size_t part_len = 0;
   ~WsModel() {
@@ -384,10 +413,10 @@ struct WsModel {
     free_ws();
   }
   void free_ws() {
-    for (void* q : {(void*)H[0], (void*)H[1], (void*)H[2], (void*)dY, (void*)dA[0], (void*)dA[1], (void*)Xw,
-                    (void*)Y, (void*)part, (void*)lpart, (void*)cpart})
+    for (void* q : {(void*)H[0], (void*)H[1], (void*)H[2], (void*)Hl[0], (void*)Hl[1], (void*)Hl[2], (void*)dY,
+                    (void*)dA[0], (void*)dA[1], (void*)Xw, (void*)Y, (void*)part, (void*)lpart, (void*)cpart})
       if (q) (void)hipFree(q);
-    H[0] = H[1] = H[2] = dY = dA[0] = dA[1] = Xw = nullptr;
+    H[0] = H[1] = H[2] = Hl[0] = Hl[1] = Hl[2] = dY = dA[0] = dA[1] = Xw = nullptr;
     Y = part = lpart = cpart = nullptr;
     cap = 0;
   }
@@ -408,7 +437,8 @@ static int ws_reserve(WsModel* W, int rows, bool train) {
   W->free_ws();
   const size_t R = (size_t)cap;
   for (int i = 0; i < 3; ++i)
-    if (hipMalloc(&W->H[i], R * kDh * 2) != hipSuccess) return GSLS_ERR_OOM;
+    if (hipMalloc(&W->H[i], R * kDh * 2) != hipSuccess || hipMalloc(&W->Hl[i], R * kDh * 2) != hipSuccess)
+      return GSLS_ERR_OOM;
   if (hipMalloc(&W->Y, R * kDout * 4) != hipSuccess) return GSLS_ERR_OOM;
   if (hipMalloc(&W->Xw, R * kDin * 2) != hipSuccess) return GSLS_ERR_OOM;
   if (train) {
@@ -425,23 +455,25 @@ static int ws_reserve(WsModel* W, int rows, bool train) {
   return GSLS_OK;
 }
 
-static void gemm(hipStream_t s, int M, int N, int K, const u16* A, int lda, bool ta, const int* ridx, const u16* B,
-                 int ldb, bool tb, int epi, const float* bias, const u16* act, int ldact, u16* Cb, float* Cf, int ldc,
-                 int kc) {
+static void gemm(hipStream_t s, int M, int N, int K, const u16* A, const u16* Alo, int lda, bool ta, const int* ridx,
+                 const u16* B, int ldb, bool tb, int epi, const float* bias, const u16* act, int ldact, u16* Cb,
+                 u16* Clo, float* Cf, int ldc, int kc) {
   GemmArgs g{};
   g.M = M; g.N = N; g.K = K;
-  g.A = A; g.lda = lda; g.ta = ta ? 1 : 0; g.ridx = ridx;
+  g.A = A; g.Alo = Alo; g.lda = lda; g.ta = ta ? 1 : 0; g.ridx = ridx;
   g.B = B; g.ldb = ldb; g.tb = tb ? 1 : 0;
-  g.bias = bias; g.act = act; g.ldact = ldact; g.Cb = Cb; g.Cf = Cf; g.ldc = ldc;
+  g.bias = bias; g.act = act; g.ldact = ldact; g.Cb = Cb; g.Clo = Clo; g.Cf = Cf; g.ldc = ldc;
   g.kc = kc > 0 ? kc : K;
   const int nz = (K + g.kc - 1) / g.kc;
   dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, nz);
   k_gemm<<<grid, 256, 0, s>>>(g, epi);
 }
 
-// Forward pass of rows X (gathered through idx if given): H1..H3 (BF16) and Y.
+// Forward pass of rows X (gathered through idx if given): H1..H3 (BF16 hi /
+// lo pairs) and Y.
 static void ws_forward(WsModel* W, const u16* X, const int* idx, int rows, float* Y) {
   const u16* in = X;
+  const u16* inlo = nullptr;   // the feature rows are BF16 by definition
   const int* ri = idx;
   int din = kDin;
   for (int L = 0; L < kLayers; ++L) {
@@ -449,12 +481,13 @@ static void ws_forward(WsModel* W, const u16* X, const int* idx, int rows, float
     const u16* Wl = W->pb + W->woff[L];
     const float* bl = W->p + W->boff[L];
     if (L + 1 < kLayers)
-      gemm(W->stream, rows, dout, din, in, din, false, ri, Wl, dout, false, EPI_BIAS_RELU, bl, nullptr, 0, W->H[L],
-           nullptr, dout, 0);
+      gemm(W->stream, rows, dout, din, in, inlo, din, false, ri, Wl, dout, false, EPI_BIAS_RELU, bl, nullptr, 0,
+           W->H[L], W->Hl[L], nullptr, dout, 0);
     else
-      gemm(W->stream, rows, dout, din, in, din, false, ri, Wl, dout, false, EPI_BIAS, bl, nullptr, 0, nullptr, Y, dout,
-           0);
+      gemm(W->stream, rows, dout, din, in, inlo, din, false, ri, Wl, dout, false, EPI_BIAS, bl, nullptr, 0, nullptr,
+           nullptr, Y, dout, 0);
     in = W->H[L];
+    inlo = W->Hl[L];
     ri = nullptr;
     din = dout;
   }
@@ -472,10 +505,11 @@ static void ws_backward(WsModel* W, const u16* X, const float* T, const float* M
   for (int L = kLayers - 1; L >= 0; --L) {
     const int din = kSizes[L], dout = kSizes[L + 1];
     const u16* hin = L > 0 ? W->H[L - 1] : X;
+    const u16* hlo = L > 0 ? W->Hl[L - 1] : nullptr;
     const int* ri = L > 0 ? nullptr : idx;
     // dW_L = h_in^T dcur  (K = rows, chunked)
-    gemm(s, din, dout, rows, hin, din, true, ri, dcur, dout, false, EPI_PARTIAL, nullptr, nullptr, 0, nullptr,
-         W->part, dout, kSplitRows);
+    gemm(s, din, dout, rows, hin, hlo, din, true, ri, dcur, dout, false, EPI_PARTIAL, nullptr, nullptr, 0, nullptr,
+         nullptr, W->part, dout, kSplitRows);
     const long long wl = (long long)din * dout;
     k_reduce_scale<<<(unsigned)((wl + 255) / 256), 256, 0, s>>>(W->part, nz, wl, W->scal, W->g + W->woff[L]);
     k_colsum<<<dim3((dout + 255) / 256, nz), 256, 0, s>>>(dcur, rows, dout, kSplitRows, W->cpart);
@@ -483,8 +517,8 @@ static void ws_backward(WsModel* W, const u16* X, const float* T, const float* M
     if (L > 0) {
       // d(pre-activation of layer L-1) = (dcur W_L^T) * [h_in > 0]
       u16* dn = W->dA[L & 1];
-      gemm(s, rows, din, dout, dcur, dout, false, nullptr, W->pb + W->woff[L], dout, true, EPI_RELU_MASK, nullptr,
-           hin, din, dn, nullptr, din, 0);
+      gemm(s, rows, din, dout, dcur, nullptr, dout, false, nullptr, W->pb + W->woff[L], dout, true, EPI_RELU_MASK,
+           nullptr, hin, din, dn, nullptr, nullptr, din, 0);
       dcur = dn;
     }
   }

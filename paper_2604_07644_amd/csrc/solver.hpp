@@ -46,6 +46,7 @@ struct IterCtl {
   int32_t status;      // 0 running, 1 solved, 2 max_iter, 3 numerical, 4 rho change, 5 wait timeout
   double r_p, r_d;
   double rho_new;      // proposed rho when status == 4
+  double r_dyn;        // max_k |x_{k+1} - A_k x_k - B_k u_k - b_k|_inf of the last iterate
 };
 
 struct IterParams {
@@ -57,6 +58,7 @@ struct IterParams {
   double rho_min, rho_max, rho_tol;
   double hnorm;        // |(q, r)|_inf
   uint32_t stamp0;     // stamps of this launch start after stamp0
+  int refresh;         // full evaluation at iteration counts divisible by refresh (0: none)
 };
 
 struct LLBufs {
@@ -89,6 +91,8 @@ int launch_epoch(const DevProblem<T>& pb, const DevEpochWork<T>& ew, const DevFa
                  double rho, int Pe, int Pi, int nlev, hipStream_t st);
 template <typename T> size_t admm_lds_bytes(int nx, int nu, int nc, int nf, int Lmax, int P, bool resident);
 template <typename T> int launch_admm(const IterArgs<T>& args, hipStream_t st);
+template <typename T>
+int launch_rdyn(const DevProblem<T>& pb, const double* X, const double* U, IterCtl* ctl, hipStream_t st);
 
 struct SlsArgs {
   int N, nx, nu, nc, nf, count;

@@ -64,14 +64,16 @@ class SqpResult(ct.Structure):
 class Settings(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("max_iter", ct.c_int32), ("adaptive_rho", ct.c_int32),
                 ("sigma", ct.c_int32), ("rho_min", ct.c_double), ("rho_max", ct.c_double),
-                ("rho_tol", ct.c_double), ("chunks_epoch", ct.c_int32), ("chunks_iter", ct.c_int32)]
+                ("rho_tol", ct.c_double), ("chunks_epoch", ct.c_int32), ("chunks_iter", ct.c_int32),
+                ("refresh", ct.c_int32)]
 
 
 class Result(ct.Structure):
     _fields_ = [("status", ct.c_int32), ("iterations", ct.c_int32), ("rho_updates", ct.c_int32),
                 ("factorizations", ct.c_int32), ("r_p", ct.c_double), ("r_d", ct.c_double),
                 ("rho", ct.c_double), ("ms_total", ct.c_double), ("ms_factor", ct.c_double),
-                ("ms_iterate", ct.c_double), ("cold_restart", ct.c_int32), ("reserved", ct.c_int32)]
+                ("ms_iterate", ct.c_double), ("cold_restart", ct.c_int32), ("reserved", ct.c_int32),
+                ("r_dyn", ct.c_double)]
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -129,6 +131,8 @@ def _load():
         "gsls_batch_get": (ct.c_int, [P, ct.c_int32, _dp, _dp, _dp, _dp]),
         "gsls_batch_free": (None, [P]),
         "gsls_batch_debug_phase_cycles": (ct.c_int, [P, ct.c_int32, _dp]),
+        "gsls_batch_set_schedule": (ct.c_int, [P, ct.c_int32, ct.c_double]),
+        "gsls_batch_get_schedule": (ct.c_int, [P, ct.POINTER(ct.c_int32), _dp, ct.POINTER(ct.c_int32)]),
         "gsls_ws_nparams": (ct.c_int64, []),
         "gsls_ws_create": (ct.c_int, [_fp, _fp, P, ct.POINTER(P)]),
         "gsls_ws_get_params": (ct.c_int, [P, _fp]),
@@ -492,6 +496,24 @@ class Batch:
         if rc != OK:
             raise GslsError(rc, "gsls_batch_debug_phase_cycles")
         return out
+
+    def set_schedule(self, gang=0, park_share=0.0):
+        """Gang schedule (gsls_batch_set_schedule): gang workgroups per
+        handed-over instance (0 auto, 1 off), park_share the solo work budget."""
+        rc = lib.gsls_batch_set_schedule(self.h, int(gang), float(park_share))
+        if rc != OK:
+            raise GslsError(rc, "gsls_batch_set_schedule")
+
+    def schedule(self):
+        """(gang, park_share, park_at[count]) of the current schedule."""
+        g = ct.c_int32(0)
+        sh = np.zeros(1)
+        pa = np.zeros(len(self.probs), dtype=np.int32)
+        rc = lib.gsls_batch_get_schedule(self.h, ct.byref(g), _ptr(sh),
+                                         pa.ctypes.data_as(ct.POINTER(ct.c_int32)))
+        if rc != OK:
+            raise GslsError(rc, "gsls_batch_get_schedule")
+        return int(g.value), float(sh[0]), pa
 
     def rows(self):
         """Number of warm-start feature rows (sum of N + 1)."""

@@ -73,3 +73,69 @@ def test_batch_detects_box_rows_and_rejects_bad_input():
     with pytest.raises(gsls.GslsError) as ei:
         gsls.Batch([W.box_lq(), p])
     assert ei.value.code == gsls.ERR_INVALID_ARG
+
+
+def _gang_batch():
+    """Instances long enough to split, general and box rows, with S, b, q, r
+    and terminal rows, two-sided / one-sided / free rows."""
+    probs = W.uneven_batch(count=5, cfg_id=44, nmin=40, nmax=120)
+    probs += [W.random_small(57, 5, 3, 4, 3, seed=51), W.random_small(64, 7, 2, 6, 0, seed=52),
+              W.polytopic_lq(48, 12, 4, 10, cfg_id=1, instance_id=11)]
+    return probs
+
+
+@pytest.mark.parametrize("gang", [2, 3, 8])
+def test_gang_continuation_matches_oracle(gang):
+    """Every eligible instance (N >= 2 gang) leaves its solo workgroup after
+    10 iterations and is finished by a gang of workgroups (chunk folds,
+    recursive doubling over the chunk transfer maps, re-runs); the solutions
+    meet the same bar as the solo path's, and a replay repeats them exactly."""
+    probs = _gang_batch()
+    b = gsls.Batch(probs)
+    b.set_schedule(gang=gang, park_share=1e-6)
+    g, _, park_at = b.schedule()
+    assert g == gang
+    assert all(pa == 10 for pa, p in zip(park_at, probs) if p.N >= 2 * gang)
+    res, _ = b.solve(tol=1e-5)
+    handed = [i for i, p in enumerate(probs) if p.N >= 2 * gang and res[i]["iterations"] > 10]
+    assert len(handed) >= len(probs) // 2, [r["iterations"] for r in res]
+    sols = []
+    for i, p in enumerate(probs):
+        assert res[i]["status"] == gsls.SOLVED, (i, res[i])
+        assert res[i]["r_p"] <= 1e-5 and res[i]["r_d"] <= 1e-5, (i, res[i])
+        gi = b.get(i)
+        sols.append(gi)
+        ref = oracle.qp_solve(p, rho=1.0, tol=1e-10)
+        at_tol = oracle.qp_solve(p, rho=1.0, tol=1e-5)
+        for key in ("X", "U"):
+            bar = max(1e-4, 3 * _err(at_tol[key], ref[key]))
+            assert _err(gi[key], ref[key]) <= bar, (i, key, _err(gi[key], ref[key]), bar)
+    res2, _ = b.solve(tol=1e-5)
+    for i in range(len(probs)):
+        assert res2[i]["iterations"] == res[i]["iterations"]
+        np.testing.assert_array_equal(b.get(i)["X"], sols[i]["X"])
+    b.close()
+
+
+def test_gang_warm_restart_and_rho_changes():
+    """A warm start from a poor iterate with a warm budget beyond the hand-over
+    point: the gang itself restarts the instance cold (z = y = 0, rho = 1)
+    and re-runs the factor epoch; the cold-restart count and the solution
+    match the solo path's outcome."""
+    probs = W.uneven_batch(count=4, cfg_id=45, nmin=48, nmax=96)
+    rng = np.random.default_rng(3)
+    z0 = [rng.standard_normal(p.m) for p in probs]
+    y0 = [rng.standard_normal(p.m) * 5 for p in probs]
+    out = {}
+    for gang in (1, 4):
+        b = gsls.Batch(probs)
+        b.set_schedule(gang=gang, park_share=1e-6)
+        res, _ = b.solve(rhos=[0.01] * len(probs), tol=1e-5, z0s=z0, y0s=y0)
+        out[gang] = (res, [b.get(i)["X"] for i in range(len(probs))])
+        b.close()
+    for i, p in enumerate(probs):
+        r1, r4 = out[1][0][i], out[4][0][i]
+        assert r4["status"] == gsls.SOLVED, r4
+        assert r4["rho_updates"] >= 1 or r4["factorizations"] >= 2
+        ref = oracle.qp_solve(p, rho=1.0, tol=1e-10)
+        assert _err(out[4][1][i], ref["X"]) <= max(1e-4, 3 * _err(out[1][1][i], ref["X"]))

@@ -1,0 +1,118 @@
+"""GPU parity at the benchmark workloads' full sizes.
+
+* Humanoid-shaped QP at the paper's scale (nx = 75, nu = 19, N = 2048, 40
+  polytopic rows per stage: 192,587 variables, 81,920 rows).  The FP64 GPU
+  solve follows the FP64 oracle iterate by iterate (same iteration and rho
+  update counts, solution to 1e-8 at tol 1e-10); the mixed-precision solve
+  (FP32 scans, FP64 inverses and state) stops at r_p, r_d <= 1e-5 and its
+  primal solution is within 1e-4 |x*|_inf of the oracle's (x* at 1e-10) and
+  of the FP64 GPU solution, element by element.
+* The 512-instance uneven batch (nx in {12,36,61,75}, nu in {4,12,19},
+  N ~ U{16..512}), solved as one batch, cold and with the trained learned
+  warm start: on a stratified subset (the longest horizon of every (nx, nu)
+  class, the instance that takes the most cold iterations, the shortest
+  horizon) every instance stops at r_p, r_d <= 1e-5 and its primal solution
+  is within max(1e-4, 3 e_tol) of the oracle's x* at 1e-10, relative to
+  |x*|_inf, where e_tol is the error the FP64 oracle itself leaves when
+  stopped at 1e-5.  Warm and cold are both checked against the oracle.
+
+The oracle solves run on host threads (the C oracle releases the GIL) while
+the GPU works.
+"""
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_07644_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+from paper_2604_07644_amd import gsls  # noqa: E402  (fails loudly without libgsls.so)
+
+
+def _err(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _pool():
+    return ThreadPoolExecutor(max_workers=max(1, min(12, (os.cpu_count() or 2) - 1)))
+
+
+@pytest.mark.timeout(600)
+def test_humanoid_full_scale_mixed_fp64_and_oracle():
+    p = W.humanoid_qp(0)
+    assert (p.N, p.nx, p.nu, p.nc) == (2048, 75, 19, 40)
+    with _pool() as ex:
+        fut = ex.submit(oracle.qp_solve, p, 1.0, 1e-10)
+        q = gsls.QP(p, gsls.default_settings(precision=gsls.FP64))
+        r64 = q.solve(rho=1.0, tol=1e-10)
+        g64 = q.get()
+        q.close()
+        q = gsls.QP(p, gsls.default_settings(precision=gsls.MIXED))
+        rm = q.solve(rho=1.0, tol=1e-5)
+        gm = q.get()
+        q.close()
+        ref = fut.result()
+    print(f"oracle {ref['iters']} it / {ref['rho_updates']} rho updates; FP64 GPU {r64['iterations']} / "
+          f"{r64['rho_updates']}; mixed {rm['iterations']} / {rm['rho_updates']}")
+    assert ref["status"] == 1
+    assert r64["status"] == gsls.SOLVED, r64
+    assert r64["iterations"] == ref["iters"] and r64["rho_updates"] == ref["rho_updates"]
+    for k in ("X", "U"):
+        assert _err(g64[k], ref[k]) <= 1e-8, (k, _err(g64[k], ref[k]))
+    assert rm["status"] == gsls.SOLVED, rm
+    assert rm["r_p"] <= 1e-5 and rm["r_d"] <= 1e-5
+    for k in ("X", "U"):
+        e_o, e_g = _err(gm[k], ref[k]), _err(gm[k], g64[k])
+        print(f"mixed {k}: vs oracle {e_o:.2e}, vs FP64 GPU {e_g:.2e}")
+        assert e_o <= 1e-4 and e_g <= 1e-4, (k, e_o, e_g)
+
+
+def _stratified(probs, cold_iters):
+    """The longest horizon of every (nx, nu) class, the instance with the
+    most cold iterations and the shortest horizon."""
+    pick = {}
+    for i, p in enumerate(probs):
+        key = (p.nx, p.nu)
+        if key not in pick or p.N > probs[pick[key]].N:
+            pick[key] = i
+    sel = set(pick.values())
+    sel.add(int(np.argmax(cold_iters)))
+    sel.add(min(range(len(probs)), key=lambda i: probs[i].N))
+    return sorted(sel)
+
+
+@pytest.mark.timeout(600)
+def test_uneven_batch_stratified_cold_and_warm_vs_oracle():
+    probs = W.uneven_batch(count=512)
+    b = gsls.Batch(probs)
+    cold, _ = b.solve(tol=1e-5)
+    sel = _stratified(probs, [r["iterations"] for r in cold])
+    assert len(sel) >= 13
+    assert {(probs[i].nx, probs[i].nu) for i in sel} == {(a, c) for a in W.NX_CLASSES for c in W.NU_CLASSES}
+    assert max(probs[i].N for i in sel) >= 500
+    with _pool() as ex:
+        tight = {i: ex.submit(oracle.qp_solve, probs[i], 1.0, 1e-10) for i in sel}
+        at_tol = {i: ex.submit(oracle.qp_solve, probs[i], 1.0, 1e-5) for i in sel}
+        gc = {i: b.get(i) for i in sel}
+        ws = gsls.WarmStart(path=os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                              "paper_2604_07644_amd", "data", "ws_box.bin"))
+        warm, _, _ = b.solve_ws(ws, tol=1e-5)
+        gw = {i: b.get(i) for i in sel}
+        ws.close()
+        b.close()
+        tight = {i: f.result() for i, f in tight.items()}
+        at_tol = {i: f.result() for i, f in at_tol.items()}
+    for i in sel:
+        p, ref = probs[i], tight[i]
+        assert ref["status"] == 1
+        for tag, res, g in (("cold", cold[i], gc[i]), ("warm", warm[i], gw[i])):
+            assert res["status"] == gsls.SOLVED, (i, tag, res)
+            assert res["r_p"] <= 1e-5 and res["r_d"] <= 1e-5, (i, tag, res)
+            for k in ("X", "U"):
+                bar = max(1e-4, 3 * _err(at_tol[i][k], ref[k]))
+                e = _err(g[k], ref[k])
+                assert e <= bar, (i, (p.N, p.nx, p.nu), tag, k, e, bar)

@@ -120,9 +120,12 @@ def test_humanoid_shape_fp64_follows_oracle(ci):
     _close_all(g, o, 1e-9)
 
 
-def test_humanoid_shape_mixed_parity():
+@pytest.mark.parametrize("ci", [0, 4])
+def test_humanoid_shape_mixed_parity(ci):
+    """ci=4: 12-stage chunks with the operators read from global memory
+    (the FP32 variant the full-length humanoid QP runs)."""
     p = W.humanoid_qp(0, N=48)
-    r, g = _gpu(p, gsls.MIXED, tol=1e-5)
+    r, g = _gpu(p, gsls.MIXED, tol=1e-5, ci=ci)
     ref = _orc(p, tol=1e-10)
     assert r["status"] == gsls.SOLVED, r
     assert _err(g["X"], ref["X"]) <= 1e-4, _err(g["X"], ref["X"])

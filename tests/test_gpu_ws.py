@@ -1,18 +1,17 @@
 """GPU parity of the learned warm start (BF16 matrix-core MLP, feature and
 target rows, start scatter, cold-restart fallback) against the FP64 oracle.
 
-Bars.  The kernels keep weights, hidden activations and back-propagated
-deltas in BF16 and accumulate in FP32.  The oracle runs in FP64 on the same
-BF16-rounded inputs and weights and, through its ``store`` hook, keeps the
-activations and deltas rounded to BF16 at the same points, so the ReLU
-decisions are taken on the same values; what remains is FP32 accumulation
-order and the rare BF16 rounding-boundary case: relative Frobenius error
-5e-3.  Against the oracle without the hook (all FP64) the BF16 storage
-itself costs about 3e-2 on the first layer's weight gradient, bounded here
-by 6e-2.  Adam is checked on the kernel's own gradient (FP32 vs FP64
-arithmetic: 1e-5).  Feature rows are BF16 roundings of FP32 sums: 1e-2
-relative + 1e-3 absolute.  Target rows are FP32 conversions of the solver's
-FP64 state: 1e-6 relative.
+Bars.  The kernels use BF16 weights, BF16 feature rows and BF16
+back-propagated deltas, keep the hidden activations as BF16 hi / lo pairs
+(about 16 significant bits) and accumulate in FP32.  The oracle is the plain
+FP64 definition, run on the same BF16-rounded weights and inputs.  What
+separates the two is the BF16 rounding of each delta (about 2e-3 relative on
+the first layer's weight gradient), the activations' pair rounding and FP32
+accumulation order: relative Frobenius error 1e-2 for every gradient and
+the forward output, 1e-3 for the loss.  Adam is checked on the kernel's own
+gradient (FP32 vs FP64 arithmetic: 1e-5).  Feature rows are BF16 roundings
+of FP32 sums: 1e-2 relative + 1e-3 absolute.  Target rows are FP32
+conversions of the solver's FP64 state: 1e-6 relative.
 """
 import numpy as np
 import pytest
@@ -66,10 +65,8 @@ def test_forward_matches_oracle_ragged_rows():
         o += b
     thb[biases] = th[biases].astype(np.float32)
     Xb = Xd.float().cpu().numpy()
-    ref, _ = OM.forward(thb, Xb, store=_bf16_round)
-    assert _rel(Y, ref) < 5e-3, _rel(Y, ref)
     ref64, _ = OM.forward(thb, Xb)
-    assert _rel(Y, ref64) < 6e-2, _rel(Y, ref64)
+    assert _rel(Y, ref64) < 1e-2, _rel(Y, ref64)
     ws.close()
 
 
@@ -83,16 +80,15 @@ def test_gradient_matches_oracle_with_row_gather():
     loss, g = ws.loss_grad(Xd, Td, Md, idx=idx)
     thb = _bf16_round(th)
     Xs = Xd.float().cpu().numpy()[perm]
-    refL, refg = OM.loss_grad(thb, Xs, T[perm], M[perm], store=_bf16_round)
-    _, refg64 = OM.loss_grad(thb, Xs, T[perm], M[perm])
+    refL, refg = OM.loss_grad(thb, Xs, T[perm], M[perm])
     assert abs(loss - refL) <= 1e-3 * refL, (loss, refL)
     o = 0
     for li, (a, b) in enumerate(zip(OM.SIZES[:-1], OM.SIZES[1:])):
-        gw, rw, rw64 = g[o:o + a * b], refg[o:o + a * b], refg64[o:o + a * b]; o += a * b
+        gw, rw = g[o:o + a * b], refg[o:o + a * b]; o += a * b
         gb, rb = g[o:o + b], refg[o:o + b]; o += b
-        assert _rel(gw, rw) < 5e-3, (li, "W", _rel(gw, rw))
-        assert _rel(gb, rb) < 5e-3, (li, "b", _rel(gb, rb))
-        assert _rel(gw, rw64) < 6e-2, (li, "W vs FP64", _rel(gw, rw64))
+        print(f"layer {li}: W {_rel(gw, rw):.2e}  b {_rel(gb, rb):.2e}")
+        assert _rel(gw, rw) < 1e-2, (li, "W", _rel(gw, rw))
+        assert _rel(gb, rb) < 1e-2, (li, "b", _rel(gb, rb))
     ws.close()
 
 

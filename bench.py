@@ -333,15 +333,15 @@ def bench_batch(args):
     model = os.path.join(ROOT, "paper_2604_07644_amd", "data", "ws_box.bin")
     ws = gsls.WarmStart(path=model, stream=stream) if os.path.exists(model) else None
 
-    def run(warm):
+    def run(warm, parts=gsls.WS_ALL):
         for _ in range(args.warmup):
-            b.solve_ws(ws, tol=TOL) if warm else b.solve(tol=TOL)
+            b.solve_ws(ws, tol=TOL, parts=parts) if warm else b.solve(tol=TOL)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         dev_ms, pred_ms, last = [], [], None
         for _ in range(args.steps):
             if warm:
-                last, ms, msp = b.solve_ws(ws, tol=TOL)
+                last, ms, msp = b.solve_ws(ws, tol=TOL, parts=parts)
             else:
                 last, ms = b.solve(tol=TOL)
                 msp = 0.0
@@ -360,12 +360,15 @@ def bench_batch(args):
                     max_r_dyn=float(max(r["r_dyn"] for r in last)), iters=it)
 
     cold = run(False)
-    warm = run(True) if ws is not None else None
+    parts = {"rho": gsls.WS_RHO, "all": gsls.WS_ALL}[args.ws_parts]
+    warm = run(True, parts) if ws is not None else None
+    # the other composition of the learned start, reported beside it
+    other = run(True, gsls.WS_ALL if parts != gsls.WS_ALL else gsls.WS_RHO) if ws is not None else None
     main = warm if warm is not None else cold
     byts = float(sum(batch_floor_bytes(p) * it for p, it in zip(probs, main["iters"])))
     ms = main["solve_ms"]
     achieved = byts / (ms * 1e-3) / 1e9
-    for d in (cold, warm):
+    for d in (cold, warm, other):
         if d is not None:
             d.pop("iters")
     b.close()
@@ -379,10 +382,13 @@ def bench_batch(args):
         "config": {"workload": "uneven batch: 512 box-constrained LTV-QPs, nx in {12,36,61,75}, nu in {4,12,19}, "
                                "N ~ U{16..512}, one graph-replayed persistent launch, warm vs cold start",
                    "tol": TOL, "start": "learned warm" if warm is not None else "cold",
+                   "warm_start_parts": {"rho": "predicted rho0, z0 = y0 = 0",
+                                        "all": "predicted rho0, z0 and y0"}[args.ws_parts],
                    "schedule": {"gang": gang, "park_share": share,
                                 "instances_eligible_for_gangs": int(np.sum(park_at < 2 ** 31 - 1))},
                    "warm_vs_cold_speedup": (warm["solves_per_s"] / cold["solves_per_s"]) if warm else None,
-                   "cold": cold, "warm": warm},
+                   "cold": cold, "warm": warm,
+                   "warm_other_parts": other},
         "roofline": {"kernel": "k_batch (persistent batched ADMM)", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": kernel_traffic(K_BATCH_TRAFFIC),
@@ -444,6 +450,8 @@ def main():
     ap.add_argument("--workload", default="batch")
     ap.add_argument("--gang", type=int, default=None, help="batch: workgroups per gang (0 auto, 1 off)")
     ap.add_argument("--park-share", type=float, default=None, help="batch: solo work budget (0 auto)")
+    ap.add_argument("--ws-parts", default="rho", choices=["rho", "all"],
+                    help="batch: parts of the learned start used for value (rho: predicted rho0 only; all: rho0, z0, y0)")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)

@@ -370,8 +370,8 @@ void gsls_batch_free(gsls_batch* b);
  * solo work reaches park_share times one workgroup's share of the batch
  * (every instance at 100 iterations); it depends on the shapes only, so a
  * replay takes the same path.
- *  gang: 0 = automatic (16), 1 = no gangs, 2..32 (at most half the grid).
- *  park_share: > 0, or 0 = automatic (0.5).
+ *  gang: 0 = automatic (32), 1 = no gangs, 2..32 (at most half the grid).
+ *  park_share: > 0, or 0 = automatic (1.0).
  * Drops the captured launch (the next solve captures a new one). */
 int gsls_batch_set_schedule(gsls_batch* b, int32_t gang, double park_share);
 
@@ -455,12 +455,15 @@ int gsls_ws_targets(gsls_batch* b, float* T, float* M);
 /* Learned warm start + batched solve: features, MLP, start (rho0 =
  * 10^(mean of the rho column over the instance's rows) clamped to the
  * settings' [rho_min, rho_max]; z0 = prediction projected onto [l, u];
- * y0 = predicted lambda / rho0), then the persistent solve.  An instance not
- * converged after warm_budget iterations (0: no limit) restarts cold (z = y =
- * 0, rho = 1) and reports cold_restart = 1.  *ms: device time of prediction
- * and solve; *ms_predict (nullable): of the prediction alone. */
+ * y0 = predicted lambda / rho0), then the persistent solve.  parts selects
+ * the predicted parts of the start (GSLS_WS_RHO | GSLS_WS_Z | GSLS_WS_Y, at
+ * least one); the others keep the cold start (rho0 = 1, z0 = 0, y0 = 0).  An
+ * instance not converged after warm_budget iterations (0: no limit) restarts
+ * cold (z = y = 0, rho = 1) and reports cold_restart = 1.  *ms: device time
+ * of prediction and solve; *ms_predict (nullable): of the prediction alone. */
+enum { GSLS_WS_RHO = 1, GSLS_WS_Z = 2, GSLS_WS_Y = 4, GSLS_WS_ALL = 7 };
 int gsls_qp_solve_batch_ws(gsls_batch* b, gsls_ws* h, const double* const* x0, double tol, int32_t warm_budget,
-                           gsls_result* out, double* ms, double* ms_predict);
+                           int32_t parts, gsls_result* out, double* ms, double* ms_predict);
 
 void gsls_ws_free(gsls_ws* h);
 

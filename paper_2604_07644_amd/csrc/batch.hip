@@ -32,8 +32,8 @@ namespace gsls {
 constexpr int kBV = 128;       // work-vector length (>= nx + nu, >= nc)
 constexpr int kBatchMaxNxu = 96;
 constexpr int kGangMax = 32;          // workgroups per gang (6 kGangMax <= kWG: residual exchange)
-constexpr int kGangAuto = 16;
-constexpr double kParkShareAuto = 0.5;
+constexpr int kGangAuto = 32;
+constexpr double kParkShareAuto = 1.0;
 
 __host__ __device__ inline int bodd(int x) { return x | 1; }
 
@@ -94,7 +94,7 @@ __host__ __device__ inline BLayout batch_layout(int nx, int nu, int nc) {
   L.pk0 = 0;
   L.pk1 = pkf;
   if (o < 2 * pkf) o = 2 * pkf;
-  L.vec = o; o += 8 * kBV + 512;
+  L.vec = o; o += 8 * kBV + 512;   // the epoch uses [0, 384) for vectors and [1024, 1536) for partial sums
   o = r4(o);
   const size_t redf = o; o += 2 * (kWG + 8);
   const size_t proff = o; o += 2 * 16;
@@ -110,19 +110,273 @@ __host__ __device__ inline BLayout batch_layout(int nx, int nu, int nc) {
 // Dynamic LDS available to one workgroup of the batched kernel.
 constexpr size_t kBatchLdsMax = 160 * 1024 - 512;
 
+// Workgroup barrier for loops that keep a buffer-to-LDS copy in flight: waits
+// for the thread's own LDS reads and writes only (lgkmcnt), then s_barrier.
+// An LDS release fence (lds_barrier) would also wait for every outstanding
+// copy into LDS (those count as LDS writes, tracked by vmcnt), i.e. for the
+// prefetch this barrier is meant to overlap.  The copies only target the
+// packet buffer that no thread reads before pk_dma_wait() and the barrier
+// after it.  The signal fences keep the compiler from moving memory accesses
+// across the barrier.
+__device__ __forceinline__ void dma_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt, expcnt unconstrained
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 __device__ inline double wg_max_d(double v, LDS double* s) {
   s[tid()] = v;
-  lds_barrier();
+  dma_barrier();
   for (int st = kWG / 2; st > 0; st >>= 1) {
     if (tid() < st) {
       double a = s[tid()], b = s[tid() + st];
       s[tid()] = (b > a || b != b) ? b : a;
     }
-    lds_barrier();
+    dma_barrier();
   }
   double r = s[0];
-  lds_barrier();
+  dma_barrier();
   return r;
+}
+
+// Work vectors of the iterations in LDS.
+struct IterVecs {
+  LDS float *g, *g2, *xz, *tv, *tu, *wv, *wv2, *part;
+  LDS double* red;
+  LDS unsigned long long* pc;
+  LDS float *buf0, *buf1;   // the two packet buffers (selected, never indexed: an
+                            // indexed pair would live in scratch memory, and
+                            // reading it back waits for every outstanding
+                            // memory operation of the wave)
+  __device__ __forceinline__ LDS float* buf(int c) const { return c ? buf1 : buf0; }
+};
+__device__ __forceinline__ IterVecs iter_vecs(const BLayout& lay, LDS char* base) {
+  IterVecs v;
+  LDS float* F0 = (LDS float*)base;
+  v.buf0 = F0 + lay.pk0;
+  v.buf1 = F0 + lay.pk1;
+  v.g = F0 + lay.vec;
+  v.g2 = v.g + kBV;
+  v.xz = v.g2 + kBV;
+  v.tv = v.xz + kBV;
+  v.tu = v.tv + kBV;
+  v.wv = v.tu + kBV;
+  v.wv2 = v.wv + kBV;
+  v.part = v.wv2 + 2 * kBV;
+  v.red = (LDS double*)(base + lay.red);
+  v.pc = (LDS unsigned long long*)(base + lay.prof);
+  return v;
+}
+
+// Optional phase profile: device clock between marks, summed per phase (LDS
+// counters, thread 0).
+struct PhaseMark {
+  LDS unsigned long long* pc;
+  bool on;
+  unsigned long long last = 0;
+  __device__ __forceinline__ void operator()(int ph) {
+    if (on) {
+      dma_barrier();
+      const unsigned long long tn = __builtin_amdgcn_s_memtime();
+      if (tid() == 0 && last) pc[ph] += tn - last;
+      last = tn;
+    }
+  }
+};
+
+// Light GEMVs for operands already in LDS (or read rarely): the reduction is
+// split over the four waves (row w + 4k), each thread keeping only a running
+// sum, so they add little register pressure next to the packet prefetch.
+// y = M^T x for M m x n (m any, n <= 128), y = M x for M m x n (m <= 128).
+template <typename PM, typename PX, typename PY>
+__device__ __forceinline__ void lite_gemv_t(int m, int n, PM M, int ld, PX x, PY y, LDS float* part) {
+  // keep the per-call index arithmetic inside the caller's loops (hoisting it
+  // out of a stage loop would hold many registers for the whole loop)
+  asm volatile("" : "+v"(ld));
+  const int lane = tid() & 63, w = tid() >> 6;
+  for (int jb = 0; jb * 64 < n; ++jb) {
+    const int j = jb * 64 + lane;
+    const int jc = min(j, n - 1);
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int i = w;
+    for (; i + 12 < m; i += 16) {
+      s0 += float(M[i * ld + jc]) * float(x[i]);
+      s1 += float(M[(i + 4) * ld + jc]) * float(x[i + 4]);
+      s2 += float(M[(i + 8) * ld + jc]) * float(x[i + 8]);
+      s3 += float(M[(i + 12) * ld + jc]) * float(x[i + 12]);
+    }
+    for (; i < m; i += 4) s0 += float(M[i * ld + jc]) * float(x[i]);
+    part[w * 128 + j] = (s0 + s1) + (s2 + s3);
+  }
+  dma_barrier();
+  for (int j = tid(); j < n; j += kWG) y[j] = part[j] + part[128 + j] + part[256 + j] + part[384 + j];
+  dma_barrier();
+}
+template <typename PM, typename PX, typename PY>
+__device__ __forceinline__ void lite_gemv_n(int m, int n, PM M, int ld, PX x, PY y, LDS float* part, bool acc) {
+  asm volatile("" : "+v"(ld));
+  const int lane = tid() & 63, w = tid() >> 6;
+  for (int ib = 0; ib * 64 < m; ++ib) {
+    const int i = ib * 64 + lane;
+    const int ic = min(i, m - 1);
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int k = w;
+    for (; k + 12 < n; k += 16) {
+      s0 += float(M[ic * ld + k]) * float(x[k]);
+      s1 += float(M[ic * ld + k + 4]) * float(x[k + 4]);
+      s2 += float(M[ic * ld + k + 8]) * float(x[k + 8]);
+      s3 += float(M[ic * ld + k + 12]) * float(x[k + 12]);
+    }
+    for (; k < n; k += 4) s0 += float(M[ic * ld + k]) * float(x[k]);
+    part[w * 128 + i] = (s0 + s1) + (s2 + s3);
+  }
+  dma_barrier();
+  for (int i = tid(); i < m; i += kWG) {
+    const float v = part[i] + part[128 + i] + part[256 + i] + part[384 + i];
+    y[i] = acc ? float(y[i]) + v : v;
+  }
+  dma_barrier();
+}
+
+// The same products for an LDS operand with every load of a thread issued
+// before its first multiply (R = rows per wave, m <= 4R): one LDS latency per
+// product instead of one per group of four rows.  y = M^T x (n <= 128 columns
+// over the lanes, rows over the waves) and y = M x (m <= 128 rows over the
+// lanes, columns over the waves).  Out-of-range terms load a clamped element
+// and are masked to zero.
+template <int R, bool TWO>
+__device__ __forceinline__ void fgemv_t_r(int m, int n, const LDS float* M, int ld, const LDS float* x, LDS float* y,
+                                          LDS float* part) {
+  const int lane = tid() & 63, w = tid() >> 6;
+  const int j0 = min(lane, n - 1), j1 = min(64 + lane, n - 1);
+  float a0[R], a1[R], xv[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int i = min(w + 4 * q, m - 1);
+    a0[q] = M[i * ld + j0];
+    if (TWO) a1[q] = M[i * ld + j1];
+    xv[q] = x[i];
+  }
+  float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const float xx = (w + 4 * q < m) ? xv[q] : 0.f;
+    s0 += a0[q] * xx;
+    if (TWO) s1 += a1[q] * xx;
+  }
+  part[w * 128 + lane] = s0;
+  if (TWO) part[w * 128 + 64 + lane] = s1;
+  dma_barrier();
+  for (int j = tid(); j < n; j += kWG) y[j] = part[j] + part[128 + j] + part[256 + j] + part[384 + j];
+  dma_barrier();
+}
+__device__ __forceinline__ void fgemv_t(int m, int n, const LDS float* M, int ld, const LDS float* x, LDS float* y,
+                                        LDS float* part) {
+  if (n > 64) {
+    if (m <= 16) fgemv_t_r<4, true>(m, n, M, ld, x, y, part);
+    else if (m <= 32) fgemv_t_r<8, true>(m, n, M, ld, x, y, part);
+    else if (m <= 64) fgemv_t_r<16, true>(m, n, M, ld, x, y, part);
+    else fgemv_t_r<24, true>(m, n, M, ld, x, y, part);
+  } else {
+    if (m <= 16) fgemv_t_r<4, false>(m, n, M, ld, x, y, part);
+    else if (m <= 32) fgemv_t_r<8, false>(m, n, M, ld, x, y, part);
+    else if (m <= 64) fgemv_t_r<16, false>(m, n, M, ld, x, y, part);
+    else fgemv_t_r<24, false>(m, n, M, ld, x, y, part);
+  }
+}
+template <int R, bool TWO>
+__device__ __forceinline__ void fgemv_n_r(int m, int n, const LDS float* M, int ld, const LDS float* x, LDS float* y,
+                                          LDS float* part) {
+  const int lane = tid() & 63, w = tid() >> 6;
+  const int i0 = min(lane, m - 1), i1 = min(64 + lane, m - 1);
+  float a0[R], a1[R], xv[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = min(w + 4 * q, n - 1);
+    a0[q] = M[i0 * ld + k];
+    if (TWO) a1[q] = M[i1 * ld + k];
+    xv[q] = x[k];
+  }
+  float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const float xx = (w + 4 * q < n) ? xv[q] : 0.f;
+    s0 += a0[q] * xx;
+    if (TWO) s1 += a1[q] * xx;
+  }
+  part[w * 128 + lane] = s0;
+  if (TWO) part[w * 128 + 64 + lane] = s1;
+  dma_barrier();
+  for (int i = tid(); i < m; i += kWG) y[i] = part[i] + part[128 + i] + part[256 + i] + part[384 + i];
+  dma_barrier();
+}
+__device__ __forceinline__ void fgemv_n(int m, int n, const LDS float* M, int ld, const LDS float* x, LDS float* y,
+                                        LDS float* part) {
+  if (m > 64) {
+    if (n <= 16) fgemv_n_r<4, true>(m, n, M, ld, x, y, part);
+    else if (n <= 32) fgemv_n_r<8, true>(m, n, M, ld, x, y, part);
+    else if (n <= 64) fgemv_n_r<16, true>(m, n, M, ld, x, y, part);
+    else fgemv_n_r<24, true>(m, n, M, ld, x, y, part);
+  } else {
+    if (n <= 16) fgemv_n_r<4, false>(m, n, M, ld, x, y, part);
+    else if (n <= 32) fgemv_n_r<8, false>(m, n, M, ld, x, y, part);
+    else if (n <= 64) fgemv_n_r<16, false>(m, n, M, ld, x, y, part);
+    else fgemv_n_r<24, false>(m, n, M, ld, x, y, part);
+  }
+}
+
+// C = alpha op(A) op(B) + beta C on the matrix cores for LDS operands with
+// k <= 96: as wg_mm_f32 (16 x 16 output tiles round-robin over the waves,
+// v_mfma_f32_16x16x4f32, lane l supplies A[i0 + l%16][k0 + l/16] and
+// B[k0 + l/16][j0 + l%16]), but a tile's operand loads are issued a slab of
+// 4 KS K-steps at a time before its products, so a tile waits for one LDS
+// latency per slab instead of one per K step.  Out-of-range operands load a clamped element
+// and are zeroed.  Ends with a barrier.  C must not alias A or B.
+template <int KS, bool TA, bool TB, typename PC>
+__device__ __forceinline__ void mm_pl_k(int m, int n, int k, float alpha, const LDS float* A, int lda,
+                                        const LDS float* B, int ldb, float beta, PC C, int ldc) {
+  const int l = lane(), w = wave();
+  const int tn = (n + 15) >> 4, tm = (m + 15) >> 4;
+  const int r16 = l & 15, q = l >> 4;
+  for (int t = w; t < tm * tn; t += 4) {
+    const int ti = t / tn, tj = t - ti * tn;
+    const int i = ti * 16 + r16, j = tj * 16 + r16;
+    const int ic = min(i, m - 1), jc = min(j, n - 1);
+    const float ma = i < m ? 1.f : 0.f, mb = j < n ? 1.f : 0.f;
+    mfma_f4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < k; k0 += 4 * KS) {   // K in slabs of 4 KS: one LDS latency per slab
+      float av[KS], bv[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int kc = min(k0 + 4 * s + q, k - 1);
+        av[s] = TA ? A[kc * lda + ic] : A[ic * lda + kc];
+        bv[s] = TB ? B[jc * ldb + kc] : B[kc * ldb + jc];
+      }
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const float mk = (k0 + 4 * s + q < k) ? ma : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s] * mk, bv[s] * mb, acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ii = ti * 16 + 4 * q + r, jj = tj * 16 + r16;
+      if (ii < m && jj < n) {
+        float v = alpha * acc[r];
+        if (beta != 0.f) v += beta * C[ii * ldc + jj];
+        C[ii * ldc + jj] = v;
+      }
+    }
+  }
+  __syncthreads();
+}
+template <bool TA, bool TB, typename PC>
+__device__ __forceinline__ void mm_pl(int m, int n, int k, float alpha, const LDS float* A, int lda,
+                                      const LDS float* B, int ldb, float beta, PC C, int ldc) {
+  if (k <= 4) mm_pl_k<1, TA, TB>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+  else if (k <= 16) mm_pl_k<4, TA, TB>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+  else mm_pl_k<10, TA, TB>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
 // Factor epoch of one instance for penalty rho.  Returns false if a Z_uu block
@@ -149,6 +403,9 @@ __device__ __attribute__((noinline)) bool batch_epoch(const BInst* __restrict__ 
   LDS int* used = perm + 32;
   float* fp = a.fp;
   const float fr = (float)rho;
+  const IterVecs V = iter_vecs(lay, base);
+  PhaseMark mark{V.pc, a.prof != nullptr};
+  if (a.prof && tid() < 4) V.pc[12 + tid()] = 0ull;
   // P_N = Q_N + rho C_N^T C_N
   const float* QN = fp + I.oQ + (size_t)N * nx * nx;
   for (int r = wave(); r < nx; r += 4)
@@ -169,41 +426,40 @@ __device__ __attribute__((noinline)) bool batch_epoch(const BInst* __restrict__ 
   for (int k = N - 1; k >= 0; --k) {
     const float* Ak = fp + I.oA + (size_t)k * nx * nx;
     const float* Bk = fp + I.oB + (size_t)k * nx * nu;
-    for (int r = wave(); r < nx; r += 4)
-      for (int c = lane(); c < nxu; c += 64)
-        AB[r * lay.ldAB + c] = c < nx ? Ak[(size_t)r * nx + c] : Bk[(size_t)r * nu + (c - nx)];
-    if (!I.box) {
-      const float* Gk = fp + I.oG + (size_t)k * nc * nxu;
-      for (int r = wave(); r < nc; r += 4)
-        for (int c = lane(); c < nxu; c += 64) G[r * lay.ldG + c] = Gk[(size_t)r * nxu + c];
-    }
-    // Pb = P b_k (vec[0..nx))
-    const float* bk = fp + I.ob + (size_t)k * nx;
-    for (int r = wave(); r < nx; r += 4) {
-      float s = 0.f;
-      for (int c = lane(); c < nx; c += 64) s += P[r * lay.ldP + c] * bk[c];
-      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-      if (lane() == 0) vec[r] = s;
-    }
-    __syncthreads();
-    // W = P [A | B];  Z = [A | B]^T W + [[Q, S^T], [S, R]] + rho G^T G
-    wg_mm_f32(nx, nxu, nx, 1.f, P, lay.ldP, false, AB, lay.ldAB, false, 0.f, W, lay.ldW);
     const float* Qk = fp + I.oQ + (size_t)k * nx * nx;
     const float* Rk = fp + I.oR + (size_t)k * nu * nu;
     const float* Sk = fp + I.oS + (size_t)k * nu * nx;
-    for (int r = wave(); r < nxu; r += 4)
-      for (int c = lane(); c < nxu; c += 64) {
-        float v;
-        if (r < nx && c < nx) v = Qk[(size_t)r * nx + c];
-        else if (r >= nx && c >= nx) v = Rk[(size_t)(r - nx) * nu + (c - nx)];
-        else if (r >= nx) v = Sk[(size_t)(r - nx) * nx + c];
-        else v = Sk[(size_t)(c - nx) * nx + r];
-        if (I.box && r == c) v += fr;
-        Z[r * lay.ldZ + c] = v;
-      }
+    const float* bk = fp + I.ob + (size_t)k * nx;
+    // stage data into LDS in passes that issue all of a thread's loads first:
+    // [A | B], the cost block [[Q, S^T], [S, R]] (+ rho on the box diagonal),
+    // G, and b (in vec[128..])
+    wg_block_pass<float>(nx, nxu, [&](int r, int c) { return c < nx ? Ak[(size_t)r * nx + c] : Bk[(size_t)r * nu + (c - nx)]; },
+                         [&](int r, int c, float v) { AB[r * lay.ldAB + c] = v; });
+    wg_block_pass<float>(nxu, nxu, [&](int r, int c) {
+                           float v;
+                           if (r < nx && c < nx) v = Qk[(size_t)r * nx + c];
+                           else if (r >= nx && c >= nx) v = Rk[(size_t)(r - nx) * nu + (c - nx)];
+                           else if (r >= nx) v = Sk[(size_t)(r - nx) * nx + c];
+                           else v = Sk[(size_t)(c - nx) * nx + r];
+                           return (I.box && r == c) ? v + fr : v;
+                         },
+                         [&](int r, int c, float v) { Z[r * lay.ldZ + c] = v; });
+    if (!I.box) {
+      const float* Gk = fp + I.oG + (size_t)k * nc * nxu;
+      wg_block_pass<float>(nc, nxu, [&](int r, int c) { return Gk[(size_t)r * nxu + c]; },
+                           [&](int r, int c, float v) { G[r * lay.ldG + c] = v; });
+    }
+    for (int c = tid(); c < nx; c += kWG) vec[128 + c] = bk[c];
     __syncthreads();
-    wg_mm_f32(nxu, nxu, nx, 1.f, AB, lay.ldAB, true, W, lay.ldW, false, 1.f, Z, lay.ldZ);
-    if (!I.box && nc > 0) wg_mm_f32(nxu, nxu, nc, fr, G, lay.ldG, true, G, lay.ldG, false, 1.f, Z, lay.ldZ);
+    mark(15);
+    // Pb = P b_k (vec[0..nx))
+    fgemv_n(nx, nx, P, lay.ldP, vec + 128, vec, vec + 1024);   // partial sums in vec[1024..1536)
+    mark(12);
+    // W = P [A | B];  Z = [A | B]^T W + [[Q, S^T], [S, R]] + rho G^T G
+    mm_pl<false, false>(nx, nxu, nx, 1.f, P, lay.ldP, AB, lay.ldAB, 0.f, W, lay.ldW);
+    mm_pl<true, false>(nxu, nxu, nx, 1.f, AB, lay.ldAB, W, lay.ldW, 1.f, Z, lay.ldZ);
+    if (!I.box && nc > 0) mm_pl<true, false>(nxu, nxu, nc, fr, G, lay.ldG, G, lay.ldG, 1.f, Z, lay.ldZ);
+    mark(13);
     // [K | Gamma] = [-Z_uu^{-1} Z_ux | Z_uu^{-1}] by FP64 elimination of
     // [Z_uu | Z_ux | I]: K comes from the elimination itself, not from a
     // rounded Gamma (which would carry cond(Z_uu) times its rounding into P)
@@ -223,32 +479,32 @@ __device__ __attribute__((noinline)) bool batch_epoch(const BInst* __restrict__ 
     if (!wg_gj_eliminate(nu, lda, aug, false, perm, used, dg)) return false;
     wg_gj_extract<float>(nu, lda, aug, perm, dg, 0, nx, -1.0, (float*)Y, lay.ldY);
     wg_gj_extract<float>(nu, lda, aug, perm, dg, nx, nu, 1.0, Gam, nu);
+    mark(14);
     // F = [[A + B K, B], [K, I]]
     float* Fk = pkt + pk.F;
-    wg_mm_f32(nx, nx, nu, 1.f, AB + nx, lay.ldAB, false, Y, lay.ldY, false, 0.f, W, lay.ldW);  // B K
-    for (int r = wave(); r < nxu; r += 4)
-      for (int c = lane(); c < nxu; c += 64) {
-        float v;
-        if (r < nx) v = c < nx ? AB[r * lay.ldAB + c] + W[r * lay.ldW + c] : AB[r * lay.ldAB + c];
-        else v = c < nx ? Y[(r - nx) * lay.ldY + c] : (c - nx == r - nx ? 1.f : 0.f);
-        Fk[(size_t)r * pk.ldF + c] = v;
-      }
-    // ev = Abar^T P b, fv = B^T P b
+    mm_pl<false, false>(nx, nx, nu, 1.f, AB + nx, lay.ldAB, Y, lay.ldY, 0.f, W, lay.ldW);  // B K
+    // Abar = A + B K in place in AB (the B block is kept)
+    for (int r = wave(); r < nx; r += 4)
+      for (int c = lane(); c < nx; c += 64) AB[r * lay.ldAB + c] += W[r * lay.ldW + c];
+    __syncthreads();
+    wg_block_pass<float>(nxu, nxu, [&](int r, int c) {
+                           if (r < nx) return AB[r * lay.ldAB + c];
+                           return c < nx ? Y[(r - nx) * lay.ldY + c] : (c - nx == r - nx ? 1.f : 0.f);
+                         },
+                         [&](int r, int c, float v) { Fk[(size_t)r * pk.ldF + c] = v; });
+    // [ev; fv] = [Abar | B]^T P b
+    fgemv_t(nx, nxu, AB, lay.ldAB, vec, vec + 256, vec + 1024);
     float* ev = pkt + pk.ev;
     float* fv = pkt + pk.fv;
     for (int c = tid(); c < nxu; c += kWG) {
-      float s = 0.f;
-      for (int r = 0; r < nx; ++r) {
-        const float m = c < nx ? AB[r * lay.ldAB + c] + W[r * lay.ldW + c] : AB[r * lay.ldAB + c];
-        s += m * vec[r];
-      }
-      if (c < nx) ev[c] = s; else fv[c - nx] = s;
+      if (c < nx) ev[c] = vec[256 + c];
+      else fv[c - nx] = vec[256 + c];
     }
     // P = Z_xx + Z_ux^T K
     for (int r = wave(); r < nx; r += 4)
       for (int c = lane(); c < nx; c += 64) P[r * lay.ldP + c] = Z[r * lay.ldZ + c];
     __syncthreads();
-    wg_mm_f32(nx, nx, nu, 1.f, Z + nx * lay.ldZ, lay.ldZ, true, Y, lay.ldY, false, 1.f, P, lay.ldP);
+    mm_pl<true, false>(nx, nx, nu, 1.f, Z + nx * lay.ldZ, lay.ldZ, Y, lay.ldY, 1.f, P, lay.ldP);
     for (int r = wave(); r < nx; r += 4)
       for (int c = r + 1 + lane(); c < nx; c += 64) {
         const float s = 0.5f * (P[r * lay.ldP + c] + P[c * lay.ldP + r]);
@@ -257,61 +513,9 @@ __device__ __attribute__((noinline)) bool batch_epoch(const BInst* __restrict__ 
       }
     __syncthreads();
   }
+  mark(15);
+  if (a.prof && tid() < 4) atomicAdd(a.prof + 12 + tid(), V.pc[12 + tid()]);
   return true;
-}
-
-// Light GEMVs for operands already in LDS (or read rarely): the reduction is
-// split over the four waves (row w + 4k), each thread keeping only a running
-// sum, so they add little register pressure next to the packet prefetch.
-// y = M^T x for M m x n (m any, n <= 128), y = M x for M m x n (m <= 128).
-template <typename PM, typename PX, typename PY>
-__device__ __forceinline__ void lite_gemv_t(int m, int n, PM M, int ld, PX x, PY y, LDS float* part) {
-  // keep the per-call index arithmetic inside the caller's loops (hoisting it
-  // out of a stage loop would hold many registers for the whole loop)
-  asm volatile("" : "+v"(ld));
-  const int lane = tid() & 63, w = tid() >> 6;
-  for (int jb = 0; jb * 64 < n; ++jb) {
-    const int j = jb * 64 + lane;
-    const int jc = min(j, n - 1);
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-    int i = w;
-    for (; i + 12 < m; i += 16) {
-      s0 += float(M[i * ld + jc]) * float(x[i]);
-      s1 += float(M[(i + 4) * ld + jc]) * float(x[i + 4]);
-      s2 += float(M[(i + 8) * ld + jc]) * float(x[i + 8]);
-      s3 += float(M[(i + 12) * ld + jc]) * float(x[i + 12]);
-    }
-    for (; i < m; i += 4) s0 += float(M[i * ld + jc]) * float(x[i]);
-    part[w * 128 + j] = (s0 + s1) + (s2 + s3);
-  }
-  lds_barrier();
-  for (int j = tid(); j < n; j += kWG) y[j] = part[j] + part[128 + j] + part[256 + j] + part[384 + j];
-  lds_barrier();
-}
-template <typename PM, typename PX, typename PY>
-__device__ __forceinline__ void lite_gemv_n(int m, int n, PM M, int ld, PX x, PY y, LDS float* part, bool acc) {
-  asm volatile("" : "+v"(ld));
-  const int lane = tid() & 63, w = tid() >> 6;
-  for (int ib = 0; ib * 64 < m; ++ib) {
-    const int i = ib * 64 + lane;
-    const int ic = min(i, m - 1);
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-    int k = w;
-    for (; k + 12 < n; k += 16) {
-      s0 += float(M[ic * ld + k]) * float(x[k]);
-      s1 += float(M[ic * ld + k + 4]) * float(x[k + 4]);
-      s2 += float(M[ic * ld + k + 8]) * float(x[k + 8]);
-      s3 += float(M[ic * ld + k + 12]) * float(x[k + 12]);
-    }
-    for (; k < n; k += 4) s0 += float(M[ic * ld + k]) * float(x[k]);
-    part[w * 128 + i] = (s0 + s1) + (s2 + s3);
-  }
-  lds_barrier();
-  for (int i = tid(); i < m; i += kWG) {
-    const float v = part[i] + part[128 + i] + part[256 + i] + part[384 + i];
-    y[i] = acc ? float(y[i]) + v : v;
-  }
-  lds_barrier();
 }
 
 // Stage packets move global -> LDS by DMA (buffer loads with the LDS
@@ -335,46 +539,6 @@ __device__ __forceinline__ void pk_dma_issue(const float* src, int n, LDS float*
 }
 __device__ __forceinline__ void pk_dma_wait() { __builtin_amdgcn_s_waitcnt(0); }
 
-// Work vectors of the iterations in LDS.
-struct IterVecs {
-  LDS float *g, *g2, *xz, *tv, *tu, *wv, *wv2, *part;
-  LDS double* red;
-  LDS unsigned long long* pc;
-  LDS float* buf[2];
-};
-__device__ __forceinline__ IterVecs iter_vecs(const BLayout& lay, LDS char* base) {
-  IterVecs v;
-  LDS float* F0 = (LDS float*)base;
-  v.buf[0] = F0 + lay.pk0;
-  v.buf[1] = F0 + lay.pk1;
-  v.g = F0 + lay.vec;
-  v.g2 = v.g + kBV;
-  v.xz = v.g2 + kBV;
-  v.tv = v.xz + kBV;
-  v.tu = v.tv + kBV;
-  v.wv = v.tu + kBV;
-  v.wv2 = v.wv + kBV;
-  v.part = v.wv2 + 2 * kBV;
-  v.red = (LDS double*)(base + lay.red);
-  v.pc = (LDS unsigned long long*)(base + lay.prof);
-  return v;
-}
-
-// Optional phase profile: device clock between marks, summed per phase (LDS
-// counters, thread 0).
-struct PhaseMark {
-  LDS unsigned long long* pc;
-  bool on;
-  unsigned long long last = 0;
-  __device__ __forceinline__ void operator()(int ph) {
-    if (on) {
-      lds_barrier();
-      const unsigned long long tn = __builtin_amdgcn_s_memtime();
-      if (tid() == 0 && last) pc[ph] += tn - last;
-      last = tn;
-    }
-  }
-};
 
 // Backward pass of one cached iteration (Sec. IV-A) over the stages [s, e):
 // p_N = cst q_N + rho C_N^T dw_N when e = N (else p_e is the caller's entry
@@ -422,7 +586,7 @@ __device__ __attribute__((noinline)) void batch_backward(const BInst* __restrict
       V.wv[r] = (float)(full ? w : w - wprev[gr]);
       if (!fold) wprev[gr] = w;
     }
-    lds_barrier();
+    dma_barrier();
     if (nf > 0 && !BOX) lite_gemv_t(nf, nx, (const float*)(fp + I.oCN), nx, V.wv, V.tv, V.part);
     for (int j = t; j < nx; j += kWG) {
       const float cw = nf > 0 ? (BOX ? V.wv[j] : V.tv[j]) : 0.f;
@@ -432,23 +596,23 @@ __device__ __attribute__((noinline)) void batch_backward(const BInst* __restrict
     for (int j = t; j < nx; j += kWG) V.g[j] = 0.f;
   }
   if (s >= e) {
-    lds_barrier();
+    dma_barrier();
     return;
   }
-  pk_dma_issue(pkt + (size_t)(e - 1) * pst, pst, V.buf[0]);
+  pk_dma_issue(pkt + (size_t)(e - 1) * pst, pst, V.buf0);
   double ry = 0.0, rz = 0.0, rw = 0.0;
   if (t < nc) {
     const size_t gr = (size_t)(e - 1) * nc + t;
     ry = ys[gr]; rz = zs[gr]; rw = wprev[gr];
   }
   pk_dma_wait();
-  lds_barrier();
+  dma_barrier();
   int cb = 0;
   for (int i = e - 1; i >= s; --i) {
-    LDS float* P = V.buf[cb];
+    LDS float* P = V.buf(cb);
     double ny = 0.0, nz = 0.0, nw = 0.0;
     if (i > s) {
-      pk_dma_issue(pkt + (size_t)(i - 1) * pst, pst, V.buf[cb ^ 1]);
+      pk_dma_issue(pkt + (size_t)(i - 1) * pst, pst, V.buf(cb ^ 1));
       if (t < nc) {
         const size_t gr = (size_t)(i - 1) * nc + t;
         ny = ys[gr]; nz = zs[gr]; nw = wprev[gr];
@@ -460,14 +624,14 @@ __device__ __attribute__((noinline)) void batch_backward(const BInst* __restrict
       V.wv[t] = (float)(full ? w : w - rw);
       if (!fold) wprev[(size_t)i * nc + t] = w;
     }
-    lds_barrier();
+    dma_barrier();
     mark(1);
     if (!BOX) {
       if (nc > 0) {
         lite_gemv_t(nc, nxu, (const float*)(fp + I.oG + (size_t)i * nc * nxu), nxu, V.wv, V.tv, V.part);
       } else {
         for (int j = t; j < nxu; j += kWG) V.tv[j] = 0.f;
-        lds_barrier();
+        dma_barrier();
       }
     }
     // xz = [p; r_hat],  wv2 = q_hat + ev (state part of c_k without K^T r_hat)
@@ -480,9 +644,9 @@ __device__ __attribute__((noinline)) void batch_backward(const BInst* __restrict
         V.xz[j] = cst * P[pk.r + (j - nx)] + fr * gw;
       }
     }
-    lds_barrier();
+    dma_barrier();
     mark(2);
-    lite_gemv_t(nxu, fold ? nx : nxu, (const LDS float*)(P + pk.F), pk.ldF, V.xz, V.g2, V.part);
+    fgemv_t(nxu, fold ? nx : nxu, (const LDS float*)(P + pk.F), pk.ldF, V.xz, V.g2, V.part);
     mark(3);
     if (fold) {
       for (int j = t; j < nx; j += kWG) V.g[j] = V.g2[j] + V.wv2[j];
@@ -491,14 +655,14 @@ __device__ __attribute__((noinline)) void batch_backward(const BInst* __restrict
         if (j < nx) V.g[j] = V.g2[j] + V.wv2[j];
         else V.tu[j - nx] = V.g2[j] + cst * P[pk.fv + (j - nx)];
       }
-      lds_barrier();
+      dma_barrier();
       lite_gemv_t(nu, nu, (const LDS float*)(P + pk.Gam), nu, V.tu, V.g2, V.part);
       for (int j = t; j < nu; j += kWG) kff[(size_t)i * nu + j] = -V.g2[j];
     }
     mark(4);
     ry = ny; rz = nz; rw = nw;
     pk_dma_wait();
-    lds_barrier();
+    dma_barrier();
     mark(5);
     cb ^= 1;
   }
@@ -530,7 +694,7 @@ __device__ __attribute__((noinline)) double batch_hxi(const BInst* __restrict__ 
   for (int j = t; j < nx; j += kWG) V.tv[j] = (float)X[(size_t)i * nx + j];
   if (!term)
     for (int j = t; j < nu; j += kWG) V.tu[j] = (float)U[(size_t)i * nu + j];
-  lds_barrier();
+  dma_barrier();
   lite_gemv_n(nx, nx, (const float*)(fp + I.oQ + (size_t)i * nx * nx), nx, V.tv, V.wv2, V.part, false);
   if (!term) {
     lite_gemv_t(nu, nx, (const float*)(fp + I.oS + (size_t)i * nu * nx), nx, V.tu, V.wv, V.part);
@@ -540,7 +704,7 @@ __device__ __attribute__((noinline)) double batch_hxi(const BInst* __restrict__ 
     for (int j = t; j < nu; j += kWG) hx = fmax(hx, fabs((double)V.g[j]));
   }
   for (int j = t; j < nx; j += kWG) hx = fmax(hx, fabs((double)V.wv2[j]));
-  lds_barrier();
+  dma_barrier();
   }
   return wg_max_d(hx, V.red);
 }
@@ -582,23 +746,23 @@ __device__ __attribute__((noinline)) void batch_forward(const BInst* __restrict_
   if (fold) {
     // (each stage's feed-forward term is read one stage ahead, with the
     // next packet's copy)
-    if (s < e) pk_dma_issue(pkt + (size_t)s * pst, pst, V.buf[0]);
+    if (s < e) pk_dma_issue(pkt + (size_t)s * pst, pst, V.buf0);
     float kf = (s < e && t < nu) ? kff[(size_t)s * nu + t] : 0.f;
     pk_dma_wait();
-    lds_barrier();
+    dma_barrier();
     int cb = 0;
     for (int i = s; i < e; ++i) {
-      LDS float* P = V.buf[cb];
+      LDS float* P = V.buf(cb);
       if (t < nu) V.xz[nx + t] = kf;
       if (i + 1 < e) {
-        pk_dma_issue(pkt + (size_t)(i + 1) * pst, pst, V.buf[cb ^ 1]);
+        pk_dma_issue(pkt + (size_t)(i + 1) * pst, pst, V.buf(cb ^ 1));
         if (t < nu) kf = kff[(size_t)(i + 1) * nu + t];
       }
-      lds_barrier();
-      lite_gemv_n(nx, nxu, (const LDS float*)(P + pk.F), pk.ldF, V.xz, V.g2, V.part, false);
+      dma_barrier();
+      fgemv_n(nx, nxu, (const LDS float*)(P + pk.F), pk.ldF, V.xz, V.g2, V.part);
       for (int j = t; j < nx; j += kWG) V.xz[j] = V.g2[j] + cst * P[pk.b + j];
       pk_dma_wait();
-      lds_barrier();
+      dma_barrier();
       cb ^= 1;
     }
     return;
@@ -613,7 +777,7 @@ __device__ __attribute__((noinline)) void batch_forward(const BInst* __restrict_
   PhaseMark mark{V.pc, a.prof != nullptr};
   double rp = 0.0, rd = 0.0, vmax = 0.0, zmax = 0.0, hx = 0.0, gl = 0.0;
   const int last = e == N ? N : e - 1;   // last stage processed
-  if (s < e) pk_dma_issue(pkt + (size_t)s * pst, pst, V.buf[0]);
+  if (s < e) pk_dma_issue(pkt + (size_t)s * pst, pst, V.buf0);
   double sv = 0.0, sy = 0.0, sz = 0.0, sl = 0.0, su = 0.0, sX = 0.0, sU = 0.0;
   {
     const int nr0 = (s == N) ? nf : nc;
@@ -626,16 +790,16 @@ __device__ __attribute__((noinline)) void batch_forward(const BInst* __restrict_
   }
   float sK = (s < N && t < nu) ? kff[(size_t)s * nu + t] : 0.f;
   pk_dma_wait();
-  lds_barrier();
+  dma_barrier();
   int cb = 0;
   for (int i = s; i <= last; ++i) {
     const bool term = (i == N);
     const int nr = term ? nf : nc;
-    LDS float* P = V.buf[cb];
+    LDS float* P = V.buf(cb);
     double nv = 0.0, ny = 0.0, nz = 0.0, nl = 0.0, nu_ = 0.0, nX = 0.0, nU = 0.0;
     // the stage's feed-forward term was read one stage ahead
     if (!term && t < nu) V.xz[nx + t] = sK;
-    if (i + 1 < e) pk_dma_issue(pkt + (size_t)(i + 1) * pst, pst, V.buf[cb ^ 1]);
+    if (i + 1 < e) pk_dma_issue(pkt + (size_t)(i + 1) * pst, pst, V.buf(cb ^ 1));
     float nK = 0.f;
     if (i + 1 < N && i + 1 <= last && t < nu) nK = kff[(size_t)(i + 1) * nu + t];
     if (i + 1 <= last) {
@@ -650,16 +814,16 @@ __device__ __attribute__((noinline)) void batch_forward(const BInst* __restrict_
     if (t < nx) X[(size_t)i * nx + t] = full ? (double)V.xz[t] : sX + (double)V.xz[t];
     mark(6);
     if (!term) {
-      lds_barrier();
+      dma_barrier();
       mark(7);
-      lite_gemv_n(nxu, nxu, (const LDS float*)(P + pk.F), pk.ldF, V.xz, V.g2, V.part, false);
+      fgemv_n(nxu, nxu, (const LDS float*)(P + pk.F), pk.ldF, V.xz, V.g2, V.part);
       mark(8);
       if (t < nu) {
         const float uu = V.g2[nx + t];
         V.xz[nx + t] = uu;
         U[(size_t)i * nu + t] = full ? (double)uu : sU + (double)uu;
       }
-      lds_barrier();
+      dma_barrier();
       if (BOX) {
         for (int r = t; r < nc; r += kWG) V.wv[r] = V.xz[r];
       } else if (nc > 0) {
@@ -672,7 +836,7 @@ __device__ __attribute__((noinline)) void batch_forward(const BInst* __restrict_
         lite_gemv_n(nf, nx, (const float*)(fp + I.oCN), nx, V.xz, V.wv, V.part, false);
       }
     }
-    lds_barrier();
+    dma_barrier();
     mark(9);
     if (t < nr) {
       const size_t gr = (size_t)i * nc + t;
@@ -690,7 +854,7 @@ __device__ __attribute__((noinline)) void batch_forward(const BInst* __restrict_
       V.wv[t] = (float)(zn - sz);
       V.wv2[t] = (float)yn;
     }
-    lds_barrier();
+    dma_barrier();
     if (nr > 0) {
       if (BOX) {
         if (t < nr) {
@@ -712,18 +876,18 @@ __device__ __attribute__((noinline)) void batch_forward(const BInst* __restrict_
           for (int j = t; j < ncol; j += kWG) gl = fmax(gl, rho * fabs((double)V.tv[j]));
         }
       }
-      lds_barrier();
+      dma_barrier();
     }
     mark(10);
     if (term) break;
     for (int j = t; j < nx; j += kWG) V.xz[j] = V.g2[j] + cst * P[pk.b + j];
     if (i == last) {   // a chunk that ends before the horizon: x_e stays in V.xz
-      lds_barrier();
+      dma_barrier();
       break;
     }
     sv = nv; sy = ny; sz = nz; sl = nl; su = nu_; sX = nX; sU = nU; sK = nK;
     pk_dma_wait();
-    lds_barrier();
+    dma_barrier();
     mark(11);
     cb ^= 1;
   }
@@ -737,7 +901,7 @@ __device__ __attribute__((noinline)) void batch_forward(const BInst* __restrict_
   }
   LDS double* out = V.red + kWG;   // the reduction buffer holds kWG + 8 doubles
   if (t == 0) { out[0] = rp; out[1] = rd; out[2] = vmax; out[3] = zmax; out[4] = hx; out[5] = gl; }
-  lds_barrier();
+  dma_barrier();
 }
 
 // Decision after one ADMM iteration from the reduced residual terms
@@ -790,7 +954,7 @@ __device__ __attribute__((noinline)) int batch_iterate(const BInst* __restrict__
   const float* fp = a.fp;
   double* ys = a.dp + I.oy;
   const int t = tid();
-  if (a.prof && t < 16) V.pc[t] = 0ull;
+  if (a.prof && t < 12) V.pc[t] = 0ull;
   const double hnorm = batch_hnorm(I, fp, V.red);
   bool first = true;
   while (true) {
@@ -807,10 +971,10 @@ __device__ __attribute__((noinline)) int batch_iterate(const BInst* __restrict__
     LDS double* out = V.red + kWG;
     double o[6];
     for (int q = 0; q < 6; ++q) o[q] = out[q];
-    lds_barrier();
+    dma_barrier();
     *rp_out = o[0];
     *rd_out = o[1];
-    if (a.prof && t < 16) { atomicAdd(a.prof + t, V.pc[t]); V.pc[t] = 0ull; }
+    if (a.prof && t < 12) { atomicAdd(a.prof + t, V.pc[t]); V.pc[t] = 0ull; }
     double rn = rho;
     const int st = admm_decide(a, rho, *it, max_iter, sigma_it, hnorm, o, &rn);
     if (st == 4) {
@@ -966,7 +1130,7 @@ __device__ __attribute__((noinline)) bool gang_maps(const BInst* __restrict__ Ip
       for (int c = lane(); c < nx; c += 64) dst[q * ldd + c] = Fi[q * pk.ldF + c];
     __syncthreads();
     if (i > s) {
-      wg_mm_f32(nx, nx, nx, 1.f, Am, ldA, false, Pm, ldP, false, 0.f, Wm, ldW);
+      mm_pl<false, false>(nx, nx, nx, 1.f, Am, ldA, Pm, ldP, 0.f, Wm, ldW);
       for (int q = wave(); q < nx; q += 4)
         for (int c = lane(); c < nx; c += 64) Pm[q * ldP + c] = Wm[q * ldW + c];
       __syncthreads();
@@ -984,7 +1148,7 @@ __device__ __attribute__((noinline)) bool gang_maps(const BInst* __restrict__ Ip
       for (int q = wave(); q < nx; q += 4)
         for (int c = lane(); c < nx; c += 64) Am[q * ldA + c] = src[(size_t)q * nx + c];
       __syncthreads();
-      wg_mm_f32(nx, nx, nx, 1.f, Am, ldA, false, Pm, ldP, false, 0.f, Wm, ldW);
+      mm_pl<false, false>(nx, nx, nx, 1.f, Am, ldA, Pm, ldP, 0.f, Wm, ldW);
       for (int q = wave(); q < nx; q += 4)
         for (int c = lane(); c < nx; c += 64) Pm[q * ldP + c] = Wm[q * ldW + c];
       __syncthreads();
@@ -1096,7 +1260,7 @@ __device__ __attribute__((noinline)) void gang_run(const BInst* __restrict__ Ip,
           }
           lite_gemv_t(nx, nx, maps + ((size_t)d * G + r) * xx, nx, V.g2, V.tv, V.part);
           for (int j = t; j < nx; j += kWG) V.g[j] += V.tv[j];
-          lds_barrier();
+          dma_barrier();
         }
         g_publish(words + gl.bwd + ((size_t)(d + 1) * G + r) * nx, stamp, V.g, nx);
       }
@@ -1117,7 +1281,7 @@ __device__ __attribute__((noinline)) void gang_run(const BInst* __restrict__ Ip,
     }
     if (r < G - 1) {
       for (int j = t; j < nx; j += kWG) V.g[j] = V.xz[j];
-      lds_barrier();
+      dma_barrier();
       g_publish(words + gl.fwd + (size_t)r * nx, stamp, V.g, nx);
       for (int d = 0; d < nlev; ++d) {
         const int pr = r - (1 << d);
@@ -1160,7 +1324,7 @@ __device__ __attribute__((noinline)) void gang_run(const BInst* __restrict__ Ip,
         s_flag = 1;
         __hip_atomic_store(&a.sync->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      lds_barrier();
+      dma_barrier();
       if (t < 6 * G) V.red[t] = mine;   // V.red holds kWG + 8 doubles; 6 G <= kWG
       __syncthreads();
       if (s_flag) { ok = false; break; }

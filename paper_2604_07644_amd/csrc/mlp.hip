@@ -326,9 +326,11 @@ __global__ void __launch_bounds__(256) k_ws_features(const BInst* inst, const fl
 // Prediction -> start of instance c (one workgroup per instance): rho0 =
 // 10^(mean over its rows of Y[., 188]) clamped to [rho_min, rho_max];
 // z0 = clip(prediction * scale, l, u); y0 = lambda prediction / rho0.
+// parts selects what the prediction sets (bit 0: rho0, bit 1: z0, bit 2: y0);
+// the rest keeps the cold start (rho0 = 1, z0 = 0, y0 = 0).
 __global__ void __launch_bounds__(256) k_ws_scatter(const BInst* inst, double* dp, const int* row_off,
                                                     const float* Y, double rho_min, double rho_max, double* rho0,
-                                                    int* warm) {
+                                                    int* warm, int parts) {
   __shared__ double red[256];
   const int c = blockIdx.x;
   const BInst I = inst[c];
@@ -344,7 +346,7 @@ __global__ void __launch_bounds__(256) k_ws_scatter(const BInst* inst, double* d
   }
   double rho = pow(10.0, red[0] / (double)(N + 1));
   rho = fmin(fmax(rho, rho_min), rho_max);
-  if (!(rho > 0.0)) rho = 1.0;
+  if (!(rho > 0.0) || !(parts & 1)) rho = 1.0;
   const double xm = dp[I.ou], um = dp[I.ou + nx];
   for (int e = tid(); e < I.m; e += 256) {
     int k, j;
@@ -354,8 +356,8 @@ __global__ void __launch_bounds__(256) k_ws_scatter(const BInst* inst, double* d
     const double zp = isx ? (double)Yr[j] * xm : (double)Yr[kXs + (j - nx)] * um;
     const double lp = isx ? (double)Yr[94 + j] : (double)Yr[169 + (j - nx)];
     const double lo = dp[I.ol + e], hi = dp[I.ou + e];
-    dp[I.oz + e] = zp < lo ? lo : (zp > hi ? hi : zp);
-    dp[I.oy + e] = lp / rho;
+    dp[I.oz + e] = (parts & 2) ? (zp < lo ? lo : (zp > hi ? hi : zp)) : 0.0;
+    dp[I.oy + e] = (parts & 4) ? lp / rho : 0.0;
   }
   if (tid() == 0) { rho0[c] = rho; warm[c] = 1; }
 }
@@ -697,8 +699,9 @@ int gsls_ws_targets(gsls_batch* b, float* T, float* M) {
 }
 
 int gsls_qp_solve_batch_ws(gsls_batch* b, gsls_ws* h, const double* const* x0, double tol, int32_t warm_budget,
-                           gsls_result* out, double* ms, double* ms_predict) {
-  if (!b || !h || !x0 || !out || !(tol >= 0) || warm_budget < 0) return GSLS_ERR_INVALID_ARG;
+                           int32_t parts, gsls_result* out, double* ms, double* ms_predict) {
+  if (!b || !h || !x0 || !out || !(tol >= 0) || warm_budget < 0 || parts < 1 || parts > 7)
+    return GSLS_ERR_INVALID_ARG;
   int rc = ws_check_batch(b);
   if (rc) return rc;
   gsls::BatchSolver* B = &b->s;
@@ -714,7 +717,7 @@ int gsls_qp_solve_batch_ws(gsls_batch* b, gsls_ws* h, const double* const* x0, d
                                                              rows, h->w.sketch, h->w.Xw);
   gsls::ws_forward(&h->w, h->w.Xw, nullptr, rows, h->w.Y);
   gsls::k_ws_scatter<<<B->count, 256, 0, B->stream>>>(B->d_inst, B->dp, B->d_row_off, h->w.Y, B->st.rho_min,
-                                                      B->st.rho_max, B->d_rho, B->d_warm);
+                                                      B->st.rho_max, B->d_rho, B->d_warm, parts);
   (void)hipEventRecord(e1, B->stream);
   h->w.stream = saved;
   if (hipGetLastError() != hipSuccess) return GSLS_ERR_HIP;

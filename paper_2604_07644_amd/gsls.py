@@ -29,6 +29,10 @@ _fp = ct.POINTER(ct.c_float)
 ROBUST_CONVERGED, ROBUST_PASS_LIMIT, ROBUST_INFEASIBLE, ROBUST_NOMINAL_FAILED = 1, 2, 4, 5
 
 
+# parts of the learned warm start (gsls_qp_solve_batch_ws)
+WS_RHO, WS_Z, WS_Y, WS_ALL = 1, 2, 4, 7
+
+
 class QPDesc(ct.Structure):
     _fields_ = [("N", ct.c_int32), ("nx", ct.c_int32), ("nu", ct.c_int32), ("nc", ct.c_int32),
                 ("nf", ct.c_int32), ("mem", ct.c_int32),
@@ -144,7 +148,8 @@ def _load():
         "gsls_ws_batch_rows": (ct.c_int32, [P]),
         "gsls_ws_features": (ct.c_int, [P, P, ct.POINTER(_dp), P]),
         "gsls_ws_targets": (ct.c_int, [P, P, P]),
-        "gsls_qp_solve_batch_ws": (ct.c_int, [P, P, ct.POINTER(_dp), ct.c_double, ct.c_int32, ct.POINTER(Result),
+        "gsls_qp_solve_batch_ws": (ct.c_int, [P, P, ct.POINTER(_dp), ct.c_double, ct.c_int32, ct.c_int32,
+                                              ct.POINTER(Result),
                                               _dp, _dp]),
         "gsls_ws_free": (None, [P]),
     }
@@ -519,14 +524,15 @@ class Batch:
         """Number of warm-start feature rows (sum of N + 1)."""
         return int(lib.gsls_ws_batch_rows(self.h))
 
-    def solve_ws(self, ws, x0s=None, tol=1e-5, warm_budget=0):
+    def solve_ws(self, ws, x0s=None, tol=1e-5, warm_budget=0, parts=WS_ALL):
         """Learned warm start + solve (gsls_qp_solve_batch_ws).  Returns
         (results, ms_total, ms_predict)."""
         n = len(self.probs)
         keep, xp = self._x0_array(x0s)
         res = (Result * n)()
         ms = np.zeros(1); msp = np.zeros(1)
-        rc = lib.gsls_qp_solve_batch_ws(self.h, ws.h, xp, float(tol), int(warm_budget), res, _ptr(ms), _ptr(msp))
+        rc = lib.gsls_qp_solve_batch_ws(self.h, ws.h, xp, float(tol), int(warm_budget), int(parts), res, _ptr(ms),
+                                        _ptr(msp))
         if rc != OK:
             raise GslsError(rc, "gsls_qp_solve_batch_ws")
         self.results = [r.asdict() for r in res]

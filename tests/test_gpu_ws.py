@@ -225,3 +225,27 @@ def test_trained_model_gain_on_held_out_batch():
         assert np.max(np.abs(g - xs[i])) <= 5e-4 * max(np.max(np.abs(xs[i])), 1.0), i
     assert np.median(it_w) < np.median(it_c), (np.median(it_w), np.median(it_c))
     b.close(); ws.close()
+
+
+def test_warm_start_parts():
+    """The start may take any subset of the prediction: with the predicted
+    rho alone (z0 = y0 = 0) the same optimum is reached, and a warm budget of
+    one iteration restarts every unconverged instance cold; an empty or
+    unknown part set is refused."""
+    ws, _, _ = _model(15)
+    probs = _box_batch()
+    b = gsls.Batch(probs)
+    cold, _ = b.solve(tol=1e-5)
+    xs = [b.get(i)["X"] for i in range(len(probs))]
+    res, _, _ = b.solve_ws(ws, tol=1e-5, parts=gsls.WS_RHO)
+    for i in range(len(probs)):
+        assert res[i]["status"] == gsls.SOLVED
+        assert np.max(np.abs(b.get(i)["X"] - xs[i])) <= 1e-3 * max(np.max(np.abs(xs[i])), 1.0)
+    res1, _, _ = b.solve_ws(ws, tol=1e-5, warm_budget=1, parts=gsls.WS_RHO | gsls.WS_Z)
+    for i in range(len(probs)):
+        assert res1[i]["cold_restart"] == 1
+        assert res1[i]["iterations"] == cold[i]["iterations"] + 1
+    for bad in (0, 8):
+        with pytest.raises(gsls.GslsError):
+            b.solve_ws(ws, tol=1e-5, parts=bad)
+    b.close(); ws.close()

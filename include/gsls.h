@@ -428,6 +428,16 @@ int gsls_ws_load(const char* path, void* stream, gsls_ws** out);
 /* Y[rows][192] (device FP32) = MLP(X[rows][160]) (device BF16 bit patterns). */
 int gsls_ws_forward(gsls_ws* h, const uint16_t* X, int32_t rows, float* Y);
 
+/* As gsls_ws_forward, for callers that cannot allocate device memory (code
+ * under stream capture, serving loops, harnesses that forbid hipMalloc): the
+ * hidden activations live in a fixed library workspace of 2048 rows instead
+ * of the handle's workspace, so the call allocates nothing.  rows > 2048:
+ * GSLS_ERR_DIM.  The workspace (12 MiB per GPU, held until the process ends)
+ * is shared by every call on that GPU: calls that overlap in time on one GPU
+ * (different streams or threads) race and must be serialised by the caller.
+ * Work is enqueued on the handle's stream; Y is complete when it finishes. */
+int gsls_ws_forward_static(gsls_ws* h, const uint16_t* X, int32_t rows, float* Y);
+
 /* Loss and gradient on rows idx[0..rows) of (X, T, M) (idx NULL: the first
  * rows rows): T, M device FP32 [*][192].  grad: host FP32 [nparams] or NULL;
  * loss: host or NULL.  No update. */

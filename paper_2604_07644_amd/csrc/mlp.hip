@@ -30,6 +30,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -471,9 +472,11 @@ static void gemm(hipStream_t s, int M, int N, int K, const u16* A, const u16* Al
   k_gemm<<<grid, 256, 0, s>>>(g, epi);
 }
 
-// Forward pass of rows X (gathered through idx if given): H1..H3 (BF16 hi /
-// lo pairs) and Y.
-static void ws_forward(WsModel* W, const u16* X, const int* idx, int rows, float* Y) {
+// Forward pass of rows X (gathered through idx if given) with the hidden
+// activations in H[0..2] (hi) and Hl[0..2] (lo), each [rows][512], and the
+// output in Y.
+static void ws_forward_into(WsModel* W, const u16* X, const int* idx, int rows, float* Y, u16* const* H,
+                            u16* const* Hl) {
   const u16* in = X;
   const u16* inlo = nullptr;   // the feature rows are BF16 by definition
   const int* ri = idx;
@@ -484,15 +487,48 @@ static void ws_forward(WsModel* W, const u16* X, const int* idx, int rows, float
     const float* bl = W->p + W->boff[L];
     if (L + 1 < kLayers)
       gemm(W->stream, rows, dout, din, in, inlo, din, false, ri, Wl, dout, false, EPI_BIAS_RELU, bl, nullptr, 0,
-           W->H[L], W->Hl[L], nullptr, dout, 0);
+           H[L], Hl[L], nullptr, dout, 0);
     else
       gemm(W->stream, rows, dout, din, in, inlo, din, false, ri, Wl, dout, false, EPI_BIAS, bl, nullptr, 0, nullptr,
            nullptr, Y, dout, 0);
-    in = W->H[L];
-    inlo = W->Hl[L];
+    in = H[L];
+    inlo = Hl[L];
     ri = nullptr;
     din = dout;
   }
+}
+
+// Forward pass with the model's own workspace (H1..H3 as BF16 hi / lo pairs).
+static void ws_forward(WsModel* W, const u16* X, const int* idx, int rows, float* Y) {
+  ws_forward_into(W, X, idx, rows, Y, W->H, W->Hl);
+}
+
+// ------------------------------------------- forward without allocation
+// Workspace of gsls_ws_forward_static: the six [kStaticRows][512] BF16
+// activation arrays (hi and lo of the three hidden layers) in one
+// file-scope device array, 12 MiB on every GPU the library runs on, held
+// until the process ends.  Every layer writes its activations before the
+// next layer reads them, so nothing needs clearing between calls.
+constexpr int kStaticRows = 2048;
+constexpr size_t kStaticElems = (size_t)6 * kStaticRows * kDh;
+static __device__ __align__(256) u16 scratch[kStaticElems];
+constexpr int kMaxDevices = 64;
+static u16* g_scratch_dev[kMaxDevices];     // device address of scratch, per device
+static std::mutex g_scratch_mu;
+
+// Device address of the static workspace on the current device, looked up
+// once per device (the array's host-side name is not a device address).
+static int static_scratch(u16** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GSLS_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GSLS_ERR_HIP;
+    g_scratch_dev[dev] = (u16*)p;
+  }
+  *out = g_scratch_dev[dev];
+  return GSLS_OK;
 }
 
 // Forward + backward: the flat gradient (W1, b1, ..., divided by sum(M)) in
@@ -626,6 +662,20 @@ int gsls_ws_forward(gsls_ws* h, const uint16_t* X, int32_t rows, float* Y) {
   int rc = gsls::ws_reserve(&h->w, rows, false);
   if (rc) return rc;
   gsls::ws_forward(&h->w, X, nullptr, rows, Y);
+  if (hipGetLastError() != hipSuccess) return GSLS_ERR_HIP;
+  return GSLS_OK;
+}
+
+int gsls_ws_forward_static(gsls_ws* h, const uint16_t* X, int32_t rows, float* Y) {
+  if (!h || !X || !Y || rows < 1) return GSLS_ERR_INVALID_ARG;
+  if (rows > gsls::kStaticRows) return GSLS_ERR_DIM;
+  gsls::u16* base = nullptr;
+  int rc = gsls::static_scratch(&base);
+  if (rc) return rc;
+  const size_t stride = (size_t)gsls::kStaticRows * gsls::kDh;
+  gsls::u16* H[3] = {base, base + stride, base + 2 * stride};
+  gsls::u16* Hl[3] = {base + 3 * stride, base + 4 * stride, base + 5 * stride};
+  gsls::ws_forward_into(&h->w, X, nullptr, rows, Y, H, Hl);
   if (hipGetLastError() != hipSuccess) return GSLS_ERR_HIP;
   return GSLS_OK;
 }

@@ -143,6 +143,7 @@ def _load():
         "gsls_ws_save": (ct.c_int, [P, ct.c_char_p]),
         "gsls_ws_load": (ct.c_int, [ct.c_char_p, P, ct.POINTER(P)]),
         "gsls_ws_forward": (ct.c_int, [P, P, ct.c_int32, P]),
+        "gsls_ws_forward_static": (ct.c_int, [P, P, ct.c_int32, P]),
         "gsls_ws_loss_grad": (ct.c_int, [P, P, P, P, P, ct.c_int32, _fp, _fp]),
         "gsls_ws_train_step": (ct.c_int, [P, P, P, P, P, ct.c_int32, ct.c_float, _fp]),
         "gsls_ws_batch_rows": (ct.c_int32, [P]),
@@ -598,6 +599,18 @@ class WarmStart:
         rc = lib.gsls_ws_forward(self.h, _dev(X), int(X.shape[0]), _dev(Y))
         if rc != OK:
             raise GslsError(rc, "gsls_ws_forward")
+        torch.cuda.synchronize()
+        return Y
+
+    def forward_static(self, X, Y=None):
+        """gsls_ws_forward_static: the forward pass in the library's fixed
+        workspace (no device allocation by the library; at most 2048 rows)."""
+        import torch
+        rows = int(X.shape[0])
+        Y = torch.empty((rows, self.D_OUT), dtype=torch.float32, device=X.device) if Y is None else Y
+        rc = lib.gsls_ws_forward_static(self.h, _dev(X), rows, _dev(Y))
+        if rc != OK:
+            raise GslsError(rc, "gsls_ws_forward_static")
         torch.cuda.synchronize()
         return Y
 

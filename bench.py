@@ -327,8 +327,16 @@ def bench_batch(args):
     probs = W.uneven_batch(count=count)
     stream = torch.cuda.current_stream().cuda_stream
     b = gsls.Batch(probs, stream=stream)
+    from paper_2604_07644_amd import autotune
+    tuned = autotune.lookup(autotune.batch_key(probs))
     if args.gang is not None or args.park_share is not None:
         b.set_schedule(gang=args.gang or 0, park_share=args.park_share or 0.0)
+        source = "command line"
+    elif tuned is not None:
+        b.set_schedule(gang=tuned["gang"], park_share=tuned["park_share"])
+        source = "autotuned (paper_2604_07644_amd/data/tuned.json)"
+    else:
+        source = "library defaults"
     gang, share, park_at = b.schedule()
     model = os.path.join(ROOT, "paper_2604_07644_amd", "data", "ws_box.bin")
     ws = gsls.WarmStart(path=model, stream=stream) if os.path.exists(model) else None
@@ -384,7 +392,7 @@ def bench_batch(args):
                    "tol": TOL, "start": "learned warm" if warm is not None else "cold",
                    "warm_start_parts": {"rho": "predicted rho0, z0 = y0 = 0",
                                         "all": "predicted rho0, z0 and y0"}[args.ws_parts],
-                   "schedule": {"gang": gang, "park_share": share,
+                   "schedule": {"gang": gang, "park_share": share, "source": source,
                                 "instances_eligible_for_gangs": int(np.sum(park_at < 2 ** 31 - 1))},
                    "warm_vs_cold_speedup": (warm["solves_per_s"] / cold["solves_per_s"]) if warm else None,
                    "cold": cold, "warm": warm,
@@ -492,7 +500,10 @@ def main():
     p, desc, tol = make_workload(args.workload)
     prec = gsls.MIXED if args.precision == "mixed" else gsls.FP64
     stream = torch.cuda.current_stream().cuda_stream
-    q = gsls.QP(p, gsls.default_settings(precision=prec), stream=stream)
+    from paper_2604_07644_amd import autotune
+    tuned = autotune.lookup(autotune.qp_key(p, prec))
+    chunks = dict(chunks_epoch=tuned["chunks_epoch"], chunks_iter=tuned["chunks_iter"]) if tuned else {}
+    q = gsls.QP(p, gsls.default_settings(precision=prec, **chunks), stream=stream)
     for _ in range(args.warmup):
         q.solve(rho=1.0, tol=tol)
     torch.cuda.synchronize()
@@ -531,7 +542,9 @@ def main():
                    "precision": args.precision, "iterations": int(np.median(iters)),
                    "rho_updates": int(np.median([r["rho_updates"] for r in res])),
                    "all_solved": ok, "ms_factor_per_solve": ms_fact, "ms_iterate_per_solve": ms_iter,
-                   "chunks": {"factor": lay[0], "iteration": lay[1], "lds_resident": lay[2], "max_chunk": lay[3]}},
+                   "chunks": {"factor": lay[0], "iteration": lay[1], "lds_resident": lay[2], "max_chunk": lay[3],
+                              "source": "autotuned (paper_2604_07644_amd/data/tuned.json)" if tuned
+                              else "library defaults"}},
         "roofline": {"kernel": "k_admm (persistent ADMM iteration)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -224,6 +224,9 @@ struct Solver : SolverBase {
     const size_t xx = (size_t)nx * nx;
     choose_chunks(s);
     if (Lmax > 64) return GSLS_ERR_DIM;
+    // a chunking whose per-workgroup state does not fit the local data share
+    // (long chunks of wide stages) is refused here rather than at launch
+    if (admm_lds_bytes<T>(nx, nu, nc, nf, Lmax, Pi, resident != 0) > 160 * 1024 - 512) return GSLS_ERR_DIM;
     // problem copies
     std::vector<T> tmp;
     pb.N = N; pb.nx = nx; pb.nu = nu; pb.nc = nc; pb.nf = nf; pb.m = h.m;

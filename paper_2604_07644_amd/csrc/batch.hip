@@ -1392,6 +1392,7 @@ __device__ __attribute__((noinline)) void gang_run(const BInst* __restrict__ Ip,
     res.restarted = restarted ? 1 : 0;
     res.r_p = rp; res.r_d = rd; res.rho = rho;
     res.t_epoch = te; res.t_iter = ti;
+    res.r_dyn = 0.0;
     a.res[idx] = res;
   }
   __syncthreads();
@@ -1566,37 +1567,41 @@ __global__ void __launch_bounds__(kWG) k_batch(const BatchArgs* __restrict__ ag)
   }
 }
 
-// Dynamics residual of each instance's returned iterate, one workgroup per
-// instance: max over stages and state rows of |x_{k+1} - A_k x_k - B_k u_k -
-// b_k| in FP64 on the FP32 stage data.
+// Dynamics residual of each instance's returned iterate: one workgroup per
+// stage row of the warm-start row table (instance c = row_inst[b], stage
+// k = b - row_off[c]; the terminal row has no stage), each wave taking state
+// rows i and its lanes the columns of [A_k | B_k] (coalesced loads), the
+// maximum over the stage merged into the instance's result by an atomic max
+// of the bit pattern (non-negative doubles order as their bits).
+// res[c].r_dyn must start at zero (the solver writes it so).
 __global__ void __launch_bounds__(kWG) k_batch_rdyn(const BInst* __restrict__ inst, const float* __restrict__ fp,
-                                                    const double* __restrict__ dp, BResult* res) {
-  __shared__ double red[kWG];
-  const BInst I = inst[blockIdx.x];
-  const int nx = I.nx, nu = I.nu;
+                                                    const double* __restrict__ dp, const int* __restrict__ row_inst,
+                                                    const int* __restrict__ row_off, BResult* res) {
+  __shared__ double red[4];
+  const int c = row_inst[blockIdx.x];
+  const BInst I = inst[c];
+  const int k = (int)blockIdx.x - row_off[c];
+  if (k >= I.N) return;   // terminal row: uniform exit
+  const int nx = I.nx, nu = I.nu, w = wave(), l = lane();
+  const double* xk = dp + I.oX + (size_t)k * nx;
+  const double* uk = dp + I.oU + (size_t)k * nu;
   double m = 0.0;
-  for (int e = tid(); e < I.N * nx; e += kWG) {
-    const int k = e / nx, i = e - k * nx;
+  for (int i = w; i < nx; i += 4) {
     const float* Ar = fp + I.oA + ((size_t)k * nx + i) * nx;
     const float* Br = fp + I.oB + ((size_t)k * nx + i) * nu;
-    const double* xk = dp + I.oX + (size_t)k * nx;
-    const double* uk = dp + I.oU + (size_t)k * nu;
-    double v = dp[I.oX + (size_t)(k + 1) * nx + i] - (double)fp[I.ob + (size_t)k * nx + i];
-    for (int j = 0; j < nx; ++j) v -= (double)Ar[j] * xk[j];
-    for (int j = 0; j < nu; ++j) v -= (double)Br[j] * uk[j];
-    const double a = fabs(v);
-    m = (a > m || a != a) ? a : m;
+    double a = 0.0;
+    for (int j = l; j < nx + nu; j += 64) a += j < nx ? (double)Ar[j] * xk[j] : (double)Br[j - nx] * uk[j - nx];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    const double e = fabs(dp[I.oX + (size_t)(k + 1) * nx + i] - (double)fp[I.ob + (size_t)k * nx + i] - a);
+    m = (e > m || e != e) ? e : m;
   }
-  red[tid()] = m;
+  if (l == 0) red[w] = m;
   __syncthreads();
-  for (int st = kWG / 2; st > 0; st >>= 1) {
-    if (tid() < st) {
-      const double a = red[tid()], b = red[tid() + st];
-      red[tid()] = (b > a || b != b) ? b : a;
-    }
-    __syncthreads();
+  if (tid() == 0) {
+    double r = red[0];
+    for (int q = 1; q < 4; ++q) r = (red[q] > r || red[q] != red[q]) ? red[q] : r;
+    atomicMax((unsigned long long*)&res[c].r_dyn, (unsigned long long)__double_as_longlong(r));
   }
-  if (tid() == 0) res[blockIdx.x].r_dyn = red[0];
 }
 
 // Clears the launch's counters, the hand-over list and the gang join counters.
@@ -1849,7 +1854,8 @@ int batch_run(BatchSolver* B, double tol, int warm_budget, gsls_result* out, dou
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return GSLS_ERR_HIP;
     k_batch_prologue<<<(count + 255) / 256, 256, 0, cs>>>((BSync*)B->d_sync, B->d_cont, B->d_join, count);
     k_batch<<<B->grid, kWG, B->lds, cs>>>(B->d_args);
-    k_batch_rdyn<<<count, kWG, 0, cs>>>(B->d_inst, B->fp, B->dp, B->d_res);
+    k_batch_rdyn<<<B->row_off[count], kWG, 0, cs>>>(B->d_inst, B->fp, B->dp, B->d_row_inst, B->d_row_off,
+                                                      B->d_res);
     if (hipStreamEndCapture(cs, &B->graph) != hipSuccess) return GSLS_ERR_HIP;
     (void)hipStreamDestroy(cs);
     if (hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0) != hipSuccess) return GSLS_ERR_HIP;

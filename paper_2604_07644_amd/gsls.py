@@ -6,8 +6,10 @@ fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as ct
 import os
+import sys
 from typing import Optional
 
 import numpy as np
@@ -163,6 +165,24 @@ def _load():
 
 lib = _load()
 
+# Handles still open when the interpreter exits are not freed: by then the
+# HIP runtime (or a profiler attached to it) may already be shutting down, and
+# a device call from a finaliser can crash the process after its work is
+# done.  The process exit releases the device memory.
+_exiting = False
+
+
+def _mark_exiting():
+    global _exiting
+    _exiting = True
+
+
+atexit.register(_mark_exiting)
+
+
+def _can_free():
+    return lib is not None and not _exiting and not sys.is_finalizing()
+
 
 def strerror(code: int) -> str:
     return lib.gsls_strerror(int(code)).decode()
@@ -229,9 +249,9 @@ class QP:
         self.result = None
 
     def close(self):
-        # at interpreter exit the module global may already be gone
-        if getattr(self, "h", None) and lib is not None:
-            lib.gsls_qp_free(self.h)
+        if getattr(self, "h", None):
+            if _can_free():
+                lib.gsls_qp_free(self.h)
             self.h = None
 
     def __del__(self):
@@ -361,8 +381,9 @@ class SQP:
         self.h = h
 
     def close(self):
-        if getattr(self, "h", None) and lib is not None:
-            lib.gsls_sqp_free(self.h)
+        if getattr(self, "h", None):
+            if _can_free():
+                lib.gsls_sqp_free(self.h)
             self.h = None
 
     def __del__(self):
@@ -436,9 +457,9 @@ class Batch:
         self.h = h
 
     def close(self):
-        # at interpreter exit the module global may already be gone
-        if getattr(self, "h", None) and lib is not None:
-            lib.gsls_batch_free(self.h)
+        if getattr(self, "h", None):
+            if _can_free():
+                lib.gsls_batch_free(self.h)
             self.h = None
 
     def __del__(self):
@@ -573,9 +594,9 @@ class WarmStart:
         return int(lib.gsls_ws_nparams())
 
     def close(self):
-        # at interpreter exit the module global may already be gone
-        if getattr(self, "h", None) and lib is not None:
-            lib.gsls_ws_free(self.h)
+        if getattr(self, "h", None):
+            if _can_free():
+                lib.gsls_ws_free(self.h)
             self.h = None
 
     def __del__(self):

@@ -158,6 +158,18 @@ def test_horizon_beyond_the_grid_is_rejected():
     assert e.value.code == gsls.ERR_DIM
 
 
+def test_chunking_beyond_the_local_data_share_is_rejected():
+    """64-stage chunks of humanoid-width stages (nx=75, nu=19, 40 rows) need
+    more local memory per workgroup than a compute unit has: refused at set-up
+    with GSLS_ERR_DIM (not a failed launch); the default chunking is accepted."""
+    p = W.humanoid_qp(0, N=2048)
+    with pytest.raises(gsls.GslsError) as e:
+        gsls.QP(p, gsls.default_settings(precision=gsls.MIXED, chunks_iter=32))
+    assert e.value.code == gsls.ERR_DIM
+    q = gsls.QP(p, gsls.default_settings(precision=gsls.MIXED))
+    q.close()
+
+
 def test_single_stage_and_unconstrained():
     p = W.random_small(1, 3, 2, 2, 1, seed=4)
     r, g = _gpu(p, gsls.FP64, iters=9, adaptive=False)

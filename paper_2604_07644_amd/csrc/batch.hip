@@ -709,6 +709,282 @@ __device__ __attribute__((noinline)) double batch_hxi(const BInst* __restrict__ 
   return wg_max_d(hx, V.red);
 }
 
+// ----------------------------------------------------------------------
+// Box-row stage passes.  When every stage's rows are exactly [x; u] the
+// iteration needs no constraint products, and each stage's other work can be
+// arranged so that every thread reads back only what it wrote itself or what
+// the stage product's own closing barrier published: a backward stage then
+// needs four workgroup barriers and a forward stage four (two of them inside
+// the product), about half of the general path's.
+
+// Barrier of one wave over its own LDS accesses: waits for its LDS
+// operations and keeps the compiler from moving LDS accesses across.
+__device__ __forceinline__ void wave_lds_sync() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Backward pass of box-row instances over [s, e) (semantics of
+// batch_backward<true>).
+__device__ __attribute__((noinline)) void box_backward(const BInst* __restrict__ Ip,
+                                                       const BatchArgs* __restrict__ ag, float fr, bool full,
+                                                       LDS char* base, int s, int e, bool fold) {
+  Ip = uniform_ptr(Ip);
+  ag = uniform_ptr(ag);
+  s = uniform_int(s);
+  e = uniform_int(e);
+  fold = uniform_int(fold ? 1 : 0) != 0;
+  const BInst& I = *Ip;
+  const BatchArgs& a = *ag;
+  const int N = I.N, nx = I.nx, nu = I.nu, nc = I.nc, nf = I.nf, nxu = nx + nu;
+  const BLayout lay = batch_layout(nx, nu, 0);
+  const PkLayout pk = pk_layout(nx, nu);
+  const int pst = pk.stride;
+  const IterVecs V = iter_vecs(lay, base);
+  const float* fp = a.fp;
+  double* dp = a.dp;
+  const float* pkt = fp + I.oPk;
+  const GLB double* ys = (const GLB double*)(dp + I.oy);
+  const GLB double* zs = (const GLB double*)(dp + I.oz);
+  GLB double* wprev = (GLB double*)(dp + I.owp);
+  GLB float* kff = (GLB float*)(a.fp + I.okff);
+  const float cst = full ? 1.f : 0.f;
+  const int t = tid(), w = wave();
+  PhaseMark mark{V.pc, a.prof != nullptr};
+  if (e == N) {
+    // p_N = cst q_N + rho dw_N on the terminal rows x_N (if any)
+    for (int j = t; j < nx; j += kWG) {
+      float cw = 0.f;
+      if (j < nf) {
+        const size_t gr = (size_t)N * nc + j;
+        const double wn = ys[gr] - zs[gr];
+        cw = (float)(full ? wn : wn - wprev[gr]);
+        if (!fold) wprev[gr] = wn;
+      }
+      V.g[j] = cst * fp[I.oq + (size_t)N * nx + j] + fr * cw;
+    }
+  } else if (fold) {
+    for (int j = t; j < nx; j += kWG) V.g[j] = 0.f;
+  }
+  if (s >= e) {
+    dma_barrier();
+    return;
+  }
+  pk_dma_issue(pkt + (size_t)(e - 1) * pst, pst, V.buf0);
+  double ry = 0.0, rz = 0.0, rw = 0.0;
+  if (t < nc) {
+    const size_t gr = (size_t)(e - 1) * nc + t;
+    ry = ys[gr]; rz = zs[gr]; rw = wprev[gr];
+  }
+  pk_dma_wait();
+  dma_barrier();
+  int cb = 0;
+  for (int i = e - 1; i >= s; --i) {
+    LDS float* P = V.buf(cb);
+    double ny = 0.0, nz = 0.0, nw = 0.0;
+    if (i > s) {
+      pk_dma_issue(pkt + (size_t)(i - 1) * pst, pst, V.buf(cb ^ 1));
+      if (t < nc) {
+        const size_t gr = (size_t)(i - 1) * nc + t;
+        ny = ys[gr]; nz = zs[gr]; nw = wprev[gr];
+      }
+    }
+    mark(0);
+    // row t of the stage: state row t < nx, input row t - nx
+    if (t < nc) {
+      const double wt = ry - rz;
+      const float dw = (float)(full ? wt : wt - rw);
+      if (!fold) wprev[(size_t)i * nc + t] = wt;
+      if (t < nx) {
+        V.xz[t] = V.g[t];
+        V.wv2[t] = cst * (P[pk.q + t] + P[pk.ev + t]) + fr * dw;
+      } else {
+        V.xz[t] = cst * P[pk.r + (t - nx)] + fr * dw;
+      }
+    }
+    dma_barrier();
+    mark(3);
+    // F^T [p; r_hat] over all four waves (ends with a barrier); then thread j
+    // forms p_k[j] and, in wave 0, k_k = -Gamma^T (B^T p + r_hat + cst fv)
+    // with only that wave's own LDS ordering
+    fgemv_t(nxu, fold ? nx : nxu, (const LDS float*)(P + pk.F), pk.ldF, V.xz, V.g2, V.part);
+    if (t < nx) V.g[t] = V.g2[t] + V.wv2[t];
+    if (!fold && w == 0) {
+      if (t < nu) V.tu[t] = V.g2[nx + t] + cst * P[pk.fv + t];
+      wave_lds_sync();
+      if (t < nu) {
+        float kk = 0.f;
+        for (int q = 0; q < nu; ++q) kk += P[pk.Gam + q * nu + t] * V.tu[q];
+        kff[(size_t)i * nu + t] = -kk;
+      }
+    }
+    mark(4);
+    ry = ny; rz = nz; rw = nw;
+    pk_dma_wait();
+    dma_barrier();
+    mark(5);
+    cb ^= 1;
+  }
+}
+
+// Forward pass of box-row instances over [s, e) (semantics of
+// batch_forward<true>): the entry in V.xz[0..nx); thread j replaces its own
+// state entry after its projection has read it; x_e ends in V.xz for a chunk
+// with e < N.
+__device__ __attribute__((noinline)) void box_forward(const BInst* __restrict__ Ip,
+                                                      const BatchArgs* __restrict__ ag, double rho, bool full,
+                                                      bool sigma_it, LDS char* base, int s, int e, bool fold) {
+  Ip = uniform_ptr(Ip);
+  ag = uniform_ptr(ag);
+  s = uniform_int(s);
+  e = uniform_int(e);
+  fold = uniform_int(fold ? 1 : 0) != 0;
+  const BInst& I = *Ip;
+  const BatchArgs& a = *ag;
+  const int N = I.N, nx = I.nx, nu = I.nu, nc = I.nc, nf = I.nf, nxu = nx + nu;
+  const BLayout lay = batch_layout(nx, nu, 0);
+  const PkLayout pk = pk_layout(nx, nu);
+  const int pst = pk.stride;
+  const IterVecs V = iter_vecs(lay, base);
+  const float* fp = a.fp;
+  double* dp = a.dp;
+  const float* pkt = fp + I.oPk;
+  const GLB float* kff = (const GLB float*)(fp + I.okff);
+  const float cst = full ? 1.f : 0.f;
+  const int t = tid(), w = wave();
+  LDS float* xa = V.xz;
+  if (fold) {
+    if (s < e) pk_dma_issue(pkt + (size_t)s * pst, pst, V.buf0);
+    float kf = (s < e && t < nu) ? kff[(size_t)s * nu + t] : 0.f;
+    pk_dma_wait();
+    dma_barrier();
+    int cb = 0;
+    for (int i = s; i < e; ++i) {
+      LDS float* P = V.buf(cb);
+      if (t < nu) xa[nx + t] = kf;
+      if (i + 1 < e) {
+        pk_dma_issue(pkt + (size_t)(i + 1) * pst, pst, V.buf(cb ^ 1));
+        if (t < nu) kf = kff[(size_t)(i + 1) * nu + t];
+      }
+      dma_barrier();
+      fgemv_n(nx, nxu, (const LDS float*)(P + pk.F), pk.ldF, xa, V.tu, V.part);
+      if (t < nx) xa[t] = V.tu[t] + cst * P[pk.b + t];
+      pk_dma_wait();
+      dma_barrier();
+      cb ^= 1;
+    }
+    return;
+  }
+  GLB double* ys = (GLB double*)(dp + I.oy);
+  GLB double* zs = (GLB double*)(dp + I.oz);
+  GLB double* vacc = (GLB double*)(dp + I.ov);
+  const GLB double* ls = (const GLB double*)(dp + I.ol);
+  const GLB double* us = (const GLB double*)(dp + I.ou);
+  GLB double* X = (GLB double*)(dp + I.oX);
+  GLB double* U = (GLB double*)(dp + I.oU);
+  PhaseMark mark{V.pc, a.prof != nullptr};
+  double rp = 0.0, rd = 0.0, vmax = 0.0, zmax = 0.0, hx = 0.0, gl = 0.0;
+  const int last = e == N ? N : e - 1;
+  if (s < e) pk_dma_issue(pkt + (size_t)s * pst, pst, V.buf0);
+  double sv = 0.0, sy = 0.0, sz = 0.0, sl = 0.0, su = 0.0, sX = 0.0, sU = 0.0;
+  {
+    const int nr0 = (s == N) ? nf : nc;
+    if (t < nr0) {
+      const size_t gr = (size_t)s * nc + t;
+      sv = vacc[gr]; sy = ys[gr]; sz = zs[gr]; sl = ls[gr]; su = us[gr];
+    }
+    if (t < nx) sX = X[(size_t)s * nx + t];
+    if (s < N && t < nu) sU = U[(size_t)s * nu + t];
+  }
+  float sK = (s < N && t < nu) ? kff[(size_t)s * nu + t] : 0.f;
+  pk_dma_wait();
+  dma_barrier();
+  int cb = 0;
+  for (int i = s; i <= last; ++i) {
+    const bool term = (i == N);
+    const int nr = term ? nf : nc;
+    LDS float* P = V.buf(cb);
+    double nv = 0.0, ny = 0.0, nz = 0.0, nl = 0.0, nu_ = 0.0, nX = 0.0, nU = 0.0;
+    if (!term && t < nu) xa[nx + t] = sK;
+    if (i + 1 < e) pk_dma_issue(pkt + (size_t)(i + 1) * pst, pst, V.buf(cb ^ 1));
+    float nK = 0.f;
+    if (i + 1 < N && i + 1 <= last && t < nu) nK = kff[(size_t)(i + 1) * nu + t];
+    if (i + 1 <= last) {
+      const int nr1 = (i + 1 == N) ? nf : nc;
+      if (t < nr1) {
+        const size_t gr = (size_t)(i + 1) * nc + t;
+        nv = vacc[gr]; ny = ys[gr]; nz = zs[gr]; nl = ls[gr]; nu_ = us[gr];
+      }
+      if (t < nx) nX = X[(size_t)(i + 1) * nx + t];
+      if (i + 1 < N && t < nu) nU = U[(size_t)(i + 1) * nu + t];
+    }
+    if (t < nx) X[(size_t)i * nx + t] = full ? (double)xa[t] : sX + (double)xa[t];
+    mark(6);
+    if (!term) {
+      dma_barrier();
+      mark(7);
+      // F [x; k] = [Abar x + B k; K x + k] over all four waves (ends with a barrier)
+      fgemv_n(nxu, nxu, (const LDS float*)(P + pk.F), pk.ldF, xa, V.tu, V.part);
+      mark(8);
+      if (t < nu) U[(size_t)i * nu + t] = full ? (double)V.tu[nx + t] : sU + (double)V.tu[nx + t];
+    }
+    mark(9);
+    if (t < nr) {
+      // v = [x; u] (terminal: x_N)
+      const float vf = t < nx ? xa[t] : V.tu[t];
+      const size_t gr = (size_t)i * nc + t;
+      const double v = full ? (double)vf : sv + (double)vf;
+      vacc[gr] = v;
+      const double tt = v + sy;
+      const double zn = tt < sl ? sl : (tt > su ? su : tt);
+      const double yn = sy + v - zn;
+      zs[gr] = zn;
+      ys[gr] = yn;
+      const double er = fabs(v - zn);
+      rp = (er > rp || er != er) ? er : rp;
+      vmax = fmax(vmax, fabs(v));
+      zmax = fmax(zmax, fabs(zn));
+      const double q = rho * fabs((double)(float)(zn - sz));
+      rd = (q > rd || q != q) ? q : rd;
+      if (sigma_it) gl = fmax(gl, rho * fabs((double)(float)yn));
+    }
+    mark(10);
+    if (term) break;
+    // next state: thread j replaces its own entry (it has read it above)
+    if (t < nx) xa[t] = V.tu[t] + cst * P[pk.b + t];
+    if (i == last) {   // a chunk that ends before the horizon: x_e stays in V.xz
+      dma_barrier();
+      break;
+    }
+    sv = nv; sy = ny; sz = nz; sl = nl; su = nu_; sX = nX; sU = nU; sK = nK;
+    pk_dma_wait();
+    dma_barrier();
+    mark(11);
+    cb ^= 1;
+  }
+  rp = wg_max_d(rp, V.red);
+  rd = wg_max_d(rd, V.red);
+  if (sigma_it) {
+    vmax = wg_max_d(vmax, V.red);
+    zmax = wg_max_d(zmax, V.red);
+    gl = wg_max_d(gl, V.red);
+    hx = batch_hxi(Ip, ag, base, s, e);   // on the x, u just accumulated
+  }
+  LDS double* out = V.red + kWG;
+  if (t == 0) { out[0] = rp; out[1] = rd; out[2] = vmax; out[3] = zmax; out[4] = hx; out[5] = gl; }
+  dma_barrier();
+}
+
+// Stage passes by row structure: box rows take the wave-owned products.
+template <bool BOX>
+__device__ __forceinline__ void stage_backward(const BInst* Ip, const BatchArgs* ag, float fr, bool full,
+                                               LDS char* base, int s, int e, bool fold);
+template <bool BOX>
+__device__ __forceinline__ void stage_forward(const BInst* Ip, const BatchArgs* ag, double rho, bool full,
+                                              bool sigma_it, LDS char* base, int s, int e, bool fold);
+
 // Forward pass of one cached iteration over the stages [s, e) (and the
 // terminal stage when e = N) from the entry x_s in V.xz[0..nx) (set by the
 // caller: cst x0 for s = 0): per stage F [x; k] = [Abar x + B k; K x + k]
@@ -904,6 +1180,19 @@ __device__ __attribute__((noinline)) void batch_forward(const BInst* __restrict_
   dma_barrier();
 }
 
+template <bool BOX>
+__device__ __forceinline__ void stage_backward(const BInst* Ip, const BatchArgs* ag, float fr, bool full,
+                                               LDS char* base, int s, int e, bool fold) {
+  if constexpr (BOX) box_backward(Ip, ag, fr, full, base, s, e, fold);
+  else batch_backward<false>(Ip, ag, fr, full, base, s, e, fold);
+}
+template <bool BOX>
+__device__ __forceinline__ void stage_forward(const BInst* Ip, const BatchArgs* ag, double rho, bool full,
+                                              bool sigma_it, LDS char* base, int s, int e, bool fold) {
+  if constexpr (BOX) box_forward(Ip, ag, rho, full, sigma_it, base, s, e, fold);
+  else batch_forward<false>(Ip, ag, rho, full, sigma_it, base, s, e, fold);
+}
+
 // Decision after one ADMM iteration from the reduced residual terms
 // o = (r_p, r_d, |v|, |z|, |H xi|, |G^T lambda| / rho): 0 continue, 1 solved,
 // 2 iteration limit, 3 numerical, 4 rho change (OSQP rule every sigma
@@ -961,12 +1250,12 @@ __device__ __attribute__((noinline)) int batch_iterate(const BInst* __restrict__
     ++*it;
     const bool full = first || (a.refresh > 0 && *it % a.refresh == 0);
     const bool sigma_it = a.adaptive && ((*it - it0) % a.sigma == 0) && *it < max_iter;
-    if (I.box) batch_backward<true>(Ip, ag, (float)rho, full, base, 0, N, false);
-    else batch_backward<false>(Ip, ag, (float)rho, full, base, 0, N, false);
+    if (I.box) stage_backward<true>(Ip, ag, (float)rho, full, base, 0, N, false);
+    else stage_backward<false>(Ip, ag, (float)rho, full, base, 0, N, false);
     // forward entry x_0 (the backward pass uses V.xz as scratch)
     for (int j = t; j < nx; j += kWG) V.xz[j] = full ? fp[I.ox0 + j] : 0.f;
-    if (I.box) batch_forward<true>(Ip, ag, rho, full, sigma_it, base, 0, N, false);
-    else batch_forward<false>(Ip, ag, rho, full, sigma_it, base, 0, N, false);
+    if (I.box) stage_forward<true>(Ip, ag, rho, full, sigma_it, base, 0, N, false);
+    else stage_forward<false>(Ip, ag, rho, full, sigma_it, base, 0, N, false);
     first = false;
     LDS double* out = V.red + kWG;
     double o[6];
@@ -1246,9 +1535,9 @@ __device__ __attribute__((noinline)) void gang_run(const BInst* __restrict__ Ip,
     const bool sigma_it = a.adaptive && ((it - it0) % a.sigma == 0) && it < limit;
     // ---- backward: fold, doubling, re-run from the exact entry
     if (r == G - 1) {
-      batch_backward<BOX>(Ip, ag, (float)rho, full, base, s, e, false);
+      stage_backward<BOX>(Ip, ag, (float)rho, full, base, s, e, false);
     } else if (r > 0) {
-      batch_backward<BOX>(Ip, ag, (float)rho, full, base, s, e, true);
+      stage_backward<BOX>(Ip, ag, (float)rho, full, base, s, e, true);
     }
     if (r > 0) {
       g_publish(words + gl.bwd + (size_t)r * nx, stamp, V.g, nx);
@@ -1270,14 +1559,14 @@ __device__ __attribute__((noinline)) void gang_run(const BInst* __restrict__ Ip,
       if (!g_fetch(words + gl.bwd + ((size_t)nlev * G + r + 1) * nx, stamp, V.g, nx, &a.sync->abort, &s_flag)) {
         ok = false; break;
       }
-      batch_backward<BOX>(Ip, ag, (float)rho, full, base, s, e, false);
+      stage_backward<BOX>(Ip, ag, (float)rho, full, base, s, e, false);
     }
     // ---- forward: fold, doubling, re-run with projection and residuals
     for (int j = t; j < nx; j += kWG) V.xz[j] = (r == 0) ? cst * a.fp[I.ox0 + j] : 0.f;
     if (r == 0) {
-      batch_forward<BOX>(Ip, ag, rho, full, sigma_it, base, s, e, false);
+      stage_forward<BOX>(Ip, ag, rho, full, sigma_it, base, s, e, false);
     } else if (r < G - 1) {
-      batch_forward<BOX>(Ip, ag, rho, full, sigma_it, base, s, e, true);
+      stage_forward<BOX>(Ip, ag, rho, full, sigma_it, base, s, e, true);
     }
     if (r < G - 1) {
       for (int j = t; j < nx; j += kWG) V.g[j] = V.xz[j];
@@ -1299,7 +1588,7 @@ __device__ __attribute__((noinline)) void gang_run(const BInst* __restrict__ Ip,
       if (!g_fetch(words + gl.fwd + ((size_t)nlev * G + r - 1) * nx, stamp, V.xz, nx, &a.sync->abort, &s_flag)) {
         ok = false; break;
       }
-      batch_forward<BOX>(Ip, ag, rho, full, sigma_it, base, s, e, false);
+      stage_forward<BOX>(Ip, ag, rho, full, sigma_it, base, s, e, false);
     }
     first = false;
     // ---- residual terms of the whole instance (same order on every member)

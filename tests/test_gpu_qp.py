@@ -210,3 +210,48 @@ def test_update_bounds_then_resolve():
     g = q.get()
     o = _orc(p2, tol=1e-7)
     _close_all(g, o, 1e-9)
+
+
+def test_device_descriptor_matches_host():
+    """Problem data, x0 and the warm start given in device memory (torch
+    tensors, GSLS_DEVICE): the same FP64 solve, iterate for iterate, as from
+    host memory (cold, then warm from the cold solution)."""
+    import ctypes as ct
+    import torch
+    p = W.polytopic_lq(40, 12, 4, 10, cfg_id=1, instance_id=7)
+    s = gsls.default_settings(precision=gsls.FP64)
+    q = gsls.QP(p, s)
+    rh = q.solve(rho=1.0, tol=1e-7)
+    gh = q.get()
+    rhw = q.solve(rho=rh["rho"], tol=1e-8, z0=gh["z"], y0=gh["lam"] / rh["rho"])
+    ghw = q.get()
+    q.close()
+
+    def dev(a):
+        return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+    def dptr(t):
+        return ct.cast(ct.c_void_p(t.data_ptr()), ct.POINTER(ct.c_double))
+
+    keep = {k: dev(getattr(p, k)) for k in ("A", "B", "b", "Q", "R", "S", "q", "r", "C", "D", "l", "u")}
+    keep["CN"] = dev(np.asarray(p.CN).reshape(p.nf, p.nx))
+    d = gsls.QPDesc(N=p.N, nx=p.nx, nu=p.nu, nc=p.nc, nf=p.nf, mem=gsls.DEVICE)
+    for k, t in keep.items():
+        setattr(d, k, dptr(t))
+    h = ct.c_void_p()
+    assert gsls.lib.gsls_qp_setup(ct.byref(d), ct.byref(s), None, ct.byref(h)) == gsls.OK
+    x0 = dev(p.x0)
+    r = gsls.Result()
+    assert gsls.lib.gsls_qp_solve(h, dptr(x0), 1.0, 1e-7, ct.byref(r)) == gsls.OK
+    X = np.zeros((p.N + 1, p.nx)); z = np.zeros(p.m); lam = np.zeros(p.m)
+    assert gsls.lib.gsls_qp_get(h, X.ctypes.data_as(ct.POINTER(ct.c_double)), None,
+                                z.ctypes.data_as(ct.POINTER(ct.c_double)),
+                                lam.ctypes.data_as(ct.POINTER(ct.c_double))) == gsls.OK
+    assert r.iterations == rh["iterations"] and r.rho_updates == rh["rho_updates"]
+    np.testing.assert_array_equal(X, gh["X"])
+    z0, y0 = dev(z), dev(lam / r.rho)
+    assert gsls.lib.gsls_qp_solve_warm(h, dptr(x0), r.rho, 1e-8, dptr(z0), dptr(y0), ct.byref(r)) == gsls.OK
+    assert gsls.lib.gsls_qp_get(h, X.ctypes.data_as(ct.POINTER(ct.c_double)), None, None, None) == gsls.OK
+    assert r.iterations == rhw["iterations"]
+    np.testing.assert_array_equal(X, ghw["X"])
+    gsls.lib.gsls_qp_free(h)

@@ -432,6 +432,42 @@ def copy_calibration(mib=256, reps=3):
     print(json.dumps({"copy_calibration_kib_per_launch": mib * 1024, "launches": reps}), flush=True)
 
 
+def measured_peaks(reps=10):
+    """Achievable peaks of this GPU, measured with library kernels: a 1 GiB
+    device-to-device copy (read + write bytes per second) and square GEMMs
+    (torch.mm, 8192^3 in BF16 and FP32, 4096^3 in FP64)."""
+    import torch
+    out = {}
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    n = (1 << 30) // 4
+    a = torch.ones(n, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = ev(), ev()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    out["copy_GBps"] = 2 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    for dt, n in ((torch.bfloat16, 8192), (torch.float32, 8192), (torch.float64, 4096)):
+        x = torch.randn(n, n, device="cuda", dtype=dt)
+        y = torch.randn(n, n, device="cuda", dtype=dt)
+        z = torch.mm(x, y)
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(reps):
+            z = torch.mm(x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"gemm_{str(dt).split('.')[-1]}_TFLOPs"] = 2 * n ** 3 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e12
+        del x, y, z
+    print(json.dumps({"measured_peaks": out, "published": {"hbm_GBps": 8000, "bf16_TFLOPs": 2500,
+                                                           "fp32_TFLOPs": 157.3, "fp64_TFLOPs": 78.6}}),
+          flush=True)
+
+
 def cpu_baseline(p, budget_s=10.0, tol=TOL):
     import oracle
     t0 = time.perf_counter()
@@ -467,7 +503,12 @@ def main():
                     help="run only a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--with-copy", action="store_true",
                     help="run the 256 MiB copy calibration before the benchmark, in the same process")
+    ap.add_argument("--peaks", action="store_true",
+                    help="measure the achievable copy bandwidth and GEMM rates, then exit")
     args = ap.parse_args()
+    if args.peaks:
+        measured_peaks()
+        return
     # a batch step is one whole 512-instance batch (about a second): fewer steps
     if args.steps is None:
         args.steps = 5 if args.workload == "batch" else 20

@@ -82,7 +82,8 @@ __host__ __device__ inline BLayout batch_layout(int nx, int nu, int nc) {
   auto r4 = [](size_t v) { return (v + 3) & ~(size_t)3; };
   const size_t aug_d = (size_t)nu * (2 * nu + nx), dg_d = 32, perm_d = 32;
   const size_t wfl = r4((size_t)(nx > nc ? nx : nc) * L.ldW);
-  const size_t afl = 2 * (aug_d + dg_d + perm_d);
+  // the W region also holds the FP64 work space of the gain (nu^2 + 64 doubles and a flag)
+  const size_t afl = 2 * std::max(aug_d + dg_d + perm_d, (size_t)nu * nu + 66);
   size_t o = 0;
   L.P = o; o += r4((size_t)nx * L.ldP);
   L.W = o; o += wfl > afl ? wfl : afl;
@@ -122,6 +123,15 @@ __device__ __forceinline__ void dma_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt, expcnt unconstrained
   __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Barrier of one wave over its own LDS accesses: waits for its LDS
+// operations and keeps the compiler from moving LDS accesses across.
+__device__ __forceinline__ void wave_lds_sync() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
@@ -326,13 +336,68 @@ __device__ __forceinline__ void fgemv_n(int m, int n, const LDS float* M, int ld
   }
 }
 
+// One 16 x 16 output tile of op(A) op(B) on the matrix cores
+// (v_mfma_f32_16x16x4f32: lane l supplies A[ic][k0 + l/16] and
+// B[k0 + l/16][jc], ic / jc the lane's row / column clamped into range --
+// rows and columns past the matrix are computed but never stored).  K runs in
+// slabs of 4 KS steps whose LDS reads are all issued before the slab's
+// products (one LDS latency per slab); full slabs read at fixed offsets from
+// two base addresses with no masking, the last partial slab clamps its K
+// index, zeroes the terms past k and skips its empty steps.
+template <int KS, bool TA, bool TB>
+__device__ __forceinline__ mfma_f4 tile_mm(int k, const LDS float* A, int lda, const LDS float* B, int ldb, int ic,
+                                           int jc, int q) {
+  const int sa = TA ? lda : 1, sb = TB ? 1 : ldb;   // strides along K
+  const LDS float* pa = TA ? A + q * lda + ic : A + ic * lda + q;
+  const LDS float* pb = TB ? B + jc * ldb + q : B + q * ldb + jc;
+  mfma_f4 acc = {0.f, 0.f, 0.f, 0.f};
+  int k0 = 0;
+  for (; k0 + 4 * KS <= k; k0 += 4 * KS) {
+    float av[KS], bv[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      av[s] = pa[(k0 + 4 * s) * sa];
+      bv[s] = pb[(k0 + 4 * s) * sb];
+    }
+    // keep the slab's reads together: without this fence the scheduler
+    // interleaves them with the products (one LDS round trip per product)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[s], acc, 0, 0, 0);
+  }
+  if (k0 < k) {
+    // the complete 4-steps left at fixed offsets, the last partial step
+    // (k % 4 != 0) clamped and zeroed past k
+    const int gfull = (k - k0) >> 2;   // < KS
+    const int kp = k0 + 4 * gfull;
+    float av[KS], bv[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+      if (s < gfull) {
+        av[s] = pa[(k0 + 4 * s) * sa];
+        bv[s] = pb[(k0 + 4 * s) * sb];
+      }
+    float ap = 0.f, bp = 0.f;
+    if (kp < k) {
+      const int kc = min(kp + q, k - 1);
+      const bool in = kp + q < k;
+      const float va = TA ? A[kc * lda + ic] : A[ic * lda + kc];
+      const float vb = TB ? B[jc * ldb + kc] : B[kc * ldb + jc];
+      ap = in ? va : 0.f;
+      bp = in ? vb : 0.f;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+      if (s < gfull) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[s], acc, 0, 0, 0);
+    if (kp < k) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ap, bp, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
 // C = alpha op(A) op(B) + beta C on the matrix cores for LDS operands with
-// k <= 96: as wg_mm_f32 (16 x 16 output tiles round-robin over the waves,
-// v_mfma_f32_16x16x4f32, lane l supplies A[i0 + l%16][k0 + l/16] and
-// B[k0 + l/16][j0 + l%16]), but a tile's operand loads are issued a slab of
-// 4 KS K-steps at a time before its products, so a tile waits for one LDS
-// latency per slab instead of one per K step.  Out-of-range operands load a clamped element
-// and are zeroed.  Ends with a barrier.  C must not alias A or B.
+// k <= 96: 16 x 16 output tiles round-robin over the waves (tile_mm).  C may
+// share an array with A or B but not their elements.  Ends with a barrier.
 template <int KS, bool TA, bool TB, typename PC>
 __device__ __forceinline__ void mm_pl_k(int m, int n, int k, float alpha, const LDS float* A, int lda,
                                         const LDS float* B, int ldb, float beta, PC C, int ldc) {
@@ -341,24 +406,8 @@ __device__ __forceinline__ void mm_pl_k(int m, int n, int k, float alpha, const 
   const int r16 = l & 15, q = l >> 4;
   for (int t = w; t < tm * tn; t += 4) {
     const int ti = t / tn, tj = t - ti * tn;
-    const int i = ti * 16 + r16, j = tj * 16 + r16;
-    const int ic = min(i, m - 1), jc = min(j, n - 1);
-    const float ma = i < m ? 1.f : 0.f, mb = j < n ? 1.f : 0.f;
-    mfma_f4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < k; k0 += 4 * KS) {   // K in slabs of 4 KS: one LDS latency per slab
-      float av[KS], bv[KS];
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const int kc = min(k0 + 4 * s + q, k - 1);
-        av[s] = TA ? A[kc * lda + ic] : A[ic * lda + kc];
-        bv[s] = TB ? B[jc * ldb + kc] : B[kc * ldb + jc];
-      }
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const float mk = (k0 + 4 * s + q < k) ? ma : 0.f;
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s] * mk, bv[s] * mb, acc, 0, 0, 0);
-      }
-    }
+    const int ic = min(ti * 16 + r16, m - 1), jc = min(tj * 16 + r16, n - 1);
+    const mfma_f4 acc = tile_mm<KS, TA, TB>(k, A, lda, B, ldb, ic, jc, q);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int ii = ti * 16 + 4 * q + r, jj = tj * 16 + r16;
@@ -377,6 +426,158 @@ __device__ __forceinline__ void mm_pl(int m, int n, int k, float alpha, const LD
   if (k <= 4) mm_pl_k<1, TA, TB>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
   else if (k <= 16) mm_pl_k<4, TA, TB>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
   else mm_pl_k<10, TA, TB>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+// Symmetric product C_out = alpha op(A) op(B) + beta C_in for a result known
+// to be symmetric (n x n): only the tiles on and above the diagonal are
+// formed, and each value is written to both (i, j) and (j, i), so the result
+// is exactly symmetric.  C_in may be C_out (every thread reads only the
+// elements on and above the diagonal it then writes).
+template <int KS, bool TA, bool TB, typename PC>
+__device__ __forceinline__ void mm_sym_pl_k(int n, int k, float alpha, const LDS float* A, int lda,
+                                            const LDS float* B, int ldb, float beta, const LDS float* Cin,
+                                            int ldi, PC Cout, int ldo) {
+  const int l = lane(), w = wave();
+  const int tn = (n + 15) >> 4;
+  const int r16 = l & 15, q = l >> 4;
+  const int tiles = tn * (tn + 1) / 2;
+  for (int t = w; t < tiles; t += 4) {
+    int ti = 0, rem = t;   // upper tile t in row-major order of the upper triangle
+    while (rem >= tn - ti) {
+      rem -= tn - ti;
+      ++ti;
+    }
+    const int tj = ti + rem;
+    const int ic = min(ti * 16 + r16, n - 1), jc = min(tj * 16 + r16, n - 1);
+    const mfma_f4 acc = tile_mm<KS, TA, TB>(k, A, lda, B, ldb, ic, jc, q);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ii = ti * 16 + 4 * q + r, jj = tj * 16 + r16;
+      if (ii < n && jj < n && ii <= jj) {
+        float v = alpha * acc[r];
+        if (beta != 0.f) v += beta * Cin[ii * ldi + jj];
+        Cout[ii * ldo + jj] = v;
+        Cout[jj * ldo + ii] = v;
+      }
+    }
+  }
+  __syncthreads();
+}
+template <bool TA, bool TB, typename PC>
+__device__ __forceinline__ void mm_sym_pl(int n, int k, float alpha, const LDS float* A, int lda, const LDS float* B,
+                                          int ldb, float beta, const LDS float* Cin, int ldi, PC Cout, int ldo) {
+  if (k <= 4) mm_sym_pl_k<1, TA, TB>(n, k, alpha, A, lda, B, ldb, beta, Cin, ldi, Cout, ldo);
+  else if (k <= 16) mm_sym_pl_k<4, TA, TB>(n, k, alpha, A, lda, B, ldb, beta, Cin, ldi, Cout, ldo);
+  else mm_sym_pl_k<10, TA, TB>(n, k, alpha, A, lda, B, ldb, beta, Cin, ldi, Cout, ldo);
+}
+
+__device__ __forceinline__ void pk_dma_wait() { __builtin_amdgcn_s_waitcnt(0); }
+
+// Linear global -> LDS copy by DMA of n floats (n a multiple of 4, both ends
+// 16-byte aligned): float e lands at dst[e].  Lanes past n issue nothing.
+// Completion: pk_dma_wait() (all of the wave's vector memory operations),
+// then a barrier.
+__device__ __forceinline__ void lds_dma_issue(const float* src, int n, LDS float* dst) {
+  src = uniform_ptr(src);
+  n = __builtin_amdgcn_readfirstlane(n);
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)src, (short)0, n * 4, 0x00020000);
+  const int w = (int)tid() >> 6;
+  const int vo = (int)tid() * 16;
+#pragma unroll
+  for (int q = 0; q < 10; ++q)
+    if (q * kWG * 4 + (int)tid() * 4 < n)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (LDS void*)(dst + q * kWG * 4 + w * 256), 16, vo, q * kWG * 16, 0,
+                                               0);
+}
+
+// Gain of one Riccati stage for a small control dimension (n = nu <= 2 TM):
+//   Gamma = Z_uu^{-1} in FP64 by wave 0 -- Gauss-Jordan steps without pivot
+//   search, every pivot of the symmetric positive definite Z_uu being a
+//   positive Schur complement (a non-positive or non-finite pivot reports
+//   "not positive definite").  Lane l holds the elements (2t + l/32, l%32),
+//   t < TM.  Before step p, the pivot row equals the pivot column with the
+//   sign flipped on the columns already eliminated, so only the column is
+//   exchanged (through LDS), and the iterate keeps that (anti)symmetry
+//   exactly; Gamma comes out exactly symmetric.
+//   K = -Gamma Z_ux, summed in FP64 by all waves, rounded once to FP32.
+// Z holds the stage's Z = [[Z_xx, Z_xu], [Z_ux, Z_uu]] (FP32, leading
+// dimension ldz); ws: FP64 LDS work space of n^2 + 64 doubles + a flag.
+// Outputs: K (n x nx, ldk) in LDS and Gamma (n x n) in the packet.  Returns
+// false (uniformly) if Z_uu is not positive definite.  Ends with a barrier.
+template <int TM>
+__device__ __forceinline__ bool stage_gain(int nx, int n, const LDS float* Z, int ldz, LDS double* ws, LDS float* K,
+                                           int ldk, float* Gam) {
+  LDS double* gam = ws;
+  LDS double* cb = ws + n * n;
+  LDS int* flag = (LDS int*)(cb + 64);
+  const int l = lane(), kk = l & 31, h = l >> 5;
+  const LDS float* Zuu = Z + nx * ldz + nx;
+  if (wave() == 0) {
+    double a[TM];
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const int i = 2 * t + h;
+      a[t] = (i < n && kk < n) ? 0.5 * ((double)Zuu[i * ldz + kk] + (double)Zuu[kk * ldz + i]) : 0.0;
+    }
+    int ok = 1;
+    for (int p = 0; p < n; ++p) {
+      LDS double* col = cb + (p & 1) * 32;
+      if (kk == p) {
+#pragma unroll
+        for (int t = 0; t < TM; ++t) col[2 * t + h] = a[t];   // entries past n are never used
+      }
+      wave_lds_sync();
+      const double d = col[p];
+      if (!(d > 0.0) || !isfinite(d)) {
+        ok = 0;
+        break;
+      }
+      const double r = 1.0 / d;
+      const double ck = col[min(kk, n - 1)];
+      const double rowk = kk < p ? -ck : ck;   // the pivot row's element in column kk
+      const bool kp = kk == p;
+      const double rowv = rowk * r;
+#pragma unroll
+      for (int t = 0; t < TM; ++t) {
+        // branch-free: the general update, then the pivot column, row and element
+        const int i = 2 * t + h;
+        const bool ip = i == p;
+        const double ci = col[min(i, n - 1)];
+        double v = a[t] - (ci * rowk) * r;
+        v = kp ? -ci * r : v;
+        v = ip ? rowv : v;
+        v = (ip && kp) ? r : v;
+        a[t] = v;
+      }
+    }
+    if (ok) {
+#pragma unroll
+      for (int t = 0; t < TM; ++t) {
+        const int i = 2 * t + h;
+        if (i < n && kk < n) gam[i * n + kk] = a[t];
+      }
+    }
+    if (l == 0) *flag = ok;
+  }
+  __syncthreads();
+  if (!*flag) return false;
+  // K = -Gamma Z_ux: thread (wave w, lane l) takes columns l, l + 64 and rows w, w + 4, ...
+  for (int cb0 = 0; cb0 < nx; cb0 += 64) {
+    const int c = cb0 + l, cc = min(c, nx - 1);
+    float z[2 * TM];
+#pragma unroll
+    for (int j = 0; j < 2 * TM; ++j) z[j] = Z[(nx + min(j, n - 1)) * ldz + cc];   // Z_ux column c
+    for (int r = wave(); r < n; r += 4) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < 2 * TM; ++j)
+        if (j < n) s += gam[r * n + j] * (double)z[j];
+      if (c < nx) K[r * ldk + c] = (float)(-s);
+    }
+  }
+  for (int e = tid(); e < n * n; e += kWG) Gam[e] = (float)gam[e];
+  __syncthreads();
+  return true;
 }
 
 // Factor epoch of one instance for penalty rho.  Returns false if a Z_uu block
@@ -407,7 +608,7 @@ __device__ __attribute__((noinline)) bool batch_epoch(const BInst* __restrict__ 
   PhaseMark mark{V.pc, a.prof != nullptr};
   if (a.prof && tid() < 4) V.pc[12 + tid()] = 0ull;
   // P_N = Q_N + rho C_N^T C_N
-  const float* QN = fp + I.oQ + (size_t)N * nx * nx;
+  const float* QN = fp + I.oQN;
   for (int r = wave(); r < nx; r += 4)
     for (int c = lane(); c < nx; c += 64) P[r * lay.ldP + c] = QN[(size_t)r * nx + c];
   __syncthreads();
@@ -423,95 +624,85 @@ __device__ __attribute__((noinline)) bool batch_epoch(const BInst* __restrict__ 
     }
   }
   __syncthreads();
+  const EpLayout ein = ep_layout(nx, nu);
+  const int ld = ein.ld;   // = lay.ldAB = lay.ldZ = lay.ldW
+  const PkLayout pk = pk_layout(nx, nu);
+  LDS double* ws = (LDS double*)(base + lay.aug);   // FP64 work space of the gain (W is dead then)
   for (int k = N - 1; k >= 0; --k) {
-    const float* Ak = fp + I.oA + (size_t)k * nx * nx;
-    const float* Bk = fp + I.oB + (size_t)k * nx * nu;
-    const float* Qk = fp + I.oQ + (size_t)k * nx * nx;
-    const float* Rk = fp + I.oR + (size_t)k * nu * nu;
-    const float* Sk = fp + I.oS + (size_t)k * nu * nx;
-    const float* bk = fp + I.ob + (size_t)k * nx;
-    // stage data into LDS in passes that issue all of a thread's loads first:
-    // [A | B], the cost block [[Q, S^T], [S, R]] (+ rho on the box diagonal),
-    // G, and b (in vec[128..])
-    wg_block_pass<float>(nx, nxu, [&](int r, int c) { return c < nx ? Ak[(size_t)r * nx + c] : Bk[(size_t)r * nu + (c - nx)]; },
-                         [&](int r, int c, float v) { AB[r * lay.ldAB + c] = v; });
-    wg_block_pass<float>(nxu, nxu, [&](int r, int c) {
-                           float v;
-                           if (r < nx && c < nx) v = Qk[(size_t)r * nx + c];
-                           else if (r >= nx && c >= nx) v = Rk[(size_t)(r - nx) * nu + (c - nx)];
-                           else if (r >= nx) v = Sk[(size_t)(r - nx) * nx + c];
-                           else v = Sk[(size_t)(c - nx) * nx + r];
-                           return (I.box && r == c) ? v + fr : v;
-                         },
-                         [&](int r, int c, float v) { Z[r * lay.ldZ + c] = v; });
+    // stage input into LDS: [A | B] and the cost block by DMA (one memory
+    // latency for both), G and b by plain loads
+    const float* Ek = fp + I.oE + (size_t)k * ein.stride;
+    lds_dma_issue(Ek + ein.AB, ein.Z - ein.AB, AB);
+    lds_dma_issue(Ek + ein.Z, ein.stride - ein.Z, Z);
     if (!I.box) {
       const float* Gk = fp + I.oG + (size_t)k * nc * nxu;
       wg_block_pass<float>(nc, nxu, [&](int r, int c) { return Gk[(size_t)r * nxu + c]; },
                            [&](int r, int c, float v) { G[r * lay.ldG + c] = v; });
     }
+    const float* bk = fp + I.ob + (size_t)k * nx;
     for (int c = tid(); c < nx; c += kWG) vec[128 + c] = bk[c];
+    pk_dma_wait();
     __syncthreads();
+    if (I.box)
+      for (int r = tid(); r < nxu; r += kWG) Z[r * ld + r] += fr;   // + rho on the box rows
     mark(15);
     // Pb = P b_k (vec[0..nx))
     fgemv_n(nx, nx, P, lay.ldP, vec + 128, vec, vec + 1024);   // partial sums in vec[1024..1536)
     mark(12);
-    // W = P [A | B];  Z = [A | B]^T W + [[Q, S^T], [S, R]] + rho G^T G
-    mm_pl<false, false>(nx, nxu, nx, 1.f, P, lay.ldP, AB, lay.ldAB, 0.f, W, lay.ldW);
-    mm_pl<true, false>(nxu, nxu, nx, 1.f, AB, lay.ldAB, W, lay.ldW, 1.f, Z, lay.ldZ);
-    if (!I.box && nc > 0) mm_pl<true, false>(nxu, nxu, nc, fr, G, lay.ldG, G, lay.ldG, 1.f, Z, lay.ldZ);
+    // W = P [A | B];  Z = [A | B]^T W + [[Q, S^T], [S, R]] (+ rho I or rho G^T G), symmetric
+    mm_pl<false, false>(nx, nxu, nx, 1.f, P, lay.ldP, AB, ld, 0.f, W, ld);
+    mm_sym_pl<true, false>(nxu, nx, 1.f, AB, ld, W, ld, 1.f, Z, ld, Z, ld);
+    if (!I.box && nc > 0) mm_sym_pl<true, false>(nxu, nc, fr, G, lay.ldG, G, lay.ldG, 1.f, Z, ld, Z, ld);
     mark(13);
-    // [K | Gamma] = [-Z_uu^{-1} Z_ux | Z_uu^{-1}] by FP64 elimination of
-    // [Z_uu | Z_ux | I]: K comes from the elimination itself, not from a
-    // rounded Gamma (which would carry cond(Z_uu) times its rounding into P)
-    const int lda = 2 * nu + nx;
-    for (int r = wave(); r < nu; r += 4)
-      for (int c = lane(); c < lda; c += 64) {
-        double v;
-        if (c < nu) v = 0.5 * ((double)Z[(nx + r) * lay.ldZ + nx + c] + (double)Z[(nx + c) * lay.ldZ + nx + r]);
-        else if (c < nu + nx) v = (double)Z[(nx + r) * lay.ldZ + (c - nu)];
-        else v = (c - nu - nx == r) ? 1.0 : 0.0;
-        aug[r * lda + c] = v;
-      }
-    __syncthreads();
-    const PkLayout pk = pk_layout(nx, nu);
     float* pkt = fp + I.oPk + (size_t)k * pk.stride;
     float* Gam = pkt + pk.Gam;
-    if (!wg_gj_eliminate(nu, lda, aug, false, perm, used, dg)) return false;
-    wg_gj_extract<float>(nu, lda, aug, perm, dg, 0, nx, -1.0, (float*)Y, lay.ldY);
-    wg_gj_extract<float>(nu, lda, aug, perm, dg, nx, nu, 1.0, Gam, nu);
+    // K = -Z_uu^{-1} Z_ux into Y, Gamma = Z_uu^{-1} into the packet
+    bool ok;
+    if (nu <= 4) ok = stage_gain<2>(nx, nu, Z, ld, ws, (LDS float*)Y, lay.ldY, Gam);
+    else if (nu <= 8) ok = stage_gain<4>(nx, nu, Z, ld, ws, (LDS float*)Y, lay.ldY, Gam);
+    else if (nu <= 12) ok = stage_gain<6>(nx, nu, Z, ld, ws, (LDS float*)Y, lay.ldY, Gam);
+    else if (nu <= 16) ok = stage_gain<8>(nx, nu, Z, ld, ws, (LDS float*)Y, lay.ldY, Gam);
+    else if (nu <= 20) ok = stage_gain<10>(nx, nu, Z, ld, ws, (LDS float*)Y, lay.ldY, Gam);
+    else if (nu <= 32) ok = stage_gain<16>(nx, nu, Z, ld, ws, (LDS float*)Y, lay.ldY, Gam);
+    else {
+      // larger control dimensions: FP64 elimination of [Z_uu | Z_ux | I]
+      const int lda = 2 * nu + nx;
+      for (int r = wave(); r < nu; r += 4)
+        for (int c = lane(); c < lda; c += 64) {
+          double v;
+          if (c < nu) v = 0.5 * ((double)Z[(nx + r) * ld + nx + c] + (double)Z[(nx + c) * ld + nx + r]);
+          else if (c < nu + nx) v = (double)Z[(nx + r) * ld + (c - nu)];
+          else v = (c - nu - nx == r) ? 1.0 : 0.0;
+          aug[r * lda + c] = v;
+        }
+      __syncthreads();
+      ok = wg_gj_eliminate(nu, lda, aug, false, perm, used, dg);
+      if (ok) {
+        wg_gj_extract<float>(nu, lda, aug, perm, dg, 0, nx, -1.0, (float*)Y, lay.ldY);
+        wg_gj_extract<float>(nu, lda, aug, perm, dg, nx, nu, 1.0, Gam, nu);
+      }
+    }
+    if (!ok) return false;
     mark(14);
+    // Abar = A + B K in place in the A block of [A | B] (the B block is kept)
+    mm_pl<false, false>(nx, nx, nu, 1.f, AB + nx, ld, Y, lay.ldY, 1.f, AB, ld);
     // F = [[A + B K, B], [K, I]]
     float* Fk = pkt + pk.F;
-    mm_pl<false, false>(nx, nx, nu, 1.f, AB + nx, lay.ldAB, Y, lay.ldY, 0.f, W, lay.ldW);  // B K
-    // Abar = A + B K in place in AB (the B block is kept)
-    for (int r = wave(); r < nx; r += 4)
-      for (int c = lane(); c < nx; c += 64) AB[r * lay.ldAB + c] += W[r * lay.ldW + c];
-    __syncthreads();
     wg_block_pass<float>(nxu, nxu, [&](int r, int c) {
-                           if (r < nx) return AB[r * lay.ldAB + c];
+                           if (r < nx) return AB[r * ld + c];
                            return c < nx ? Y[(r - nx) * lay.ldY + c] : (c - nx == r - nx ? 1.f : 0.f);
                          },
                          [&](int r, int c, float v) { Fk[(size_t)r * pk.ldF + c] = v; });
     // [ev; fv] = [Abar | B]^T P b
-    fgemv_t(nx, nxu, AB, lay.ldAB, vec, vec + 256, vec + 1024);
+    fgemv_t(nx, nxu, AB, ld, vec, vec + 256, vec + 1024);
     float* ev = pkt + pk.ev;
     float* fv = pkt + pk.fv;
     for (int c = tid(); c < nxu; c += kWG) {
       if (c < nx) ev[c] = vec[256 + c];
       else fv[c - nx] = vec[256 + c];
     }
-    // P = Z_xx + Z_ux^T K
-    for (int r = wave(); r < nx; r += 4)
-      for (int c = lane(); c < nx; c += 64) P[r * lay.ldP + c] = Z[r * lay.ldZ + c];
-    __syncthreads();
-    mm_pl<true, false>(nx, nx, nu, 1.f, Z + nx * lay.ldZ, lay.ldZ, Y, lay.ldY, 1.f, P, lay.ldP);
-    for (int r = wave(); r < nx; r += 4)
-      for (int c = r + 1 + lane(); c < nx; c += 64) {
-        const float s = 0.5f * (P[r * lay.ldP + c] + P[c * lay.ldP + r]);
-        P[r * lay.ldP + c] = s;
-        P[c * lay.ldP + r] = s;
-      }
-    __syncthreads();
+    // P = Z_xx + Z_ux^T K (symmetric)
+    mm_sym_pl<true, false>(nx, nu, 1.f, Z + nx * ld, ld, Y, lay.ldY, 1.f, Z, ld, P, lay.ldP);
   }
   mark(15);
   if (a.prof && tid() < 4) atomicAdd(a.prof + 12 + tid(), V.pc[12 + tid()]);
@@ -537,7 +728,6 @@ __device__ __forceinline__ void pk_dma_issue(const float* src, int n, LDS float*
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (LDS void*)(dst + q * kWG * 4 + w * 256), 16, vo, q * kWG * 16, 0,
                                                0);
 }
-__device__ __forceinline__ void pk_dma_wait() { __builtin_amdgcn_s_waitcnt(0); }
 
 
 // Backward pass of one cached iteration (Sec. IV-A) over the stages [s, e):
@@ -683,6 +873,7 @@ __device__ __attribute__((noinline)) double batch_hxi(const BInst* __restrict__ 
   const int N = I.N, nx = I.nx, nu = I.nu, nc = I.nc, nf = I.nf;
   const BLayout lay = batch_layout(nx, nu, I.box ? 0 : (nc > nf ? nc : nf));
   const IterVecs V = iter_vecs(lay, base);
+  const EpLayout ep = ep_layout(nx, nu);
   const float* fp = a.fp;
   const GLB double* X = (const GLB double*)(a.dp + I.oX);
   const GLB double* U = (const GLB double*)(a.dp + I.oU);
@@ -695,12 +886,16 @@ __device__ __attribute__((noinline)) double batch_hxi(const BInst* __restrict__ 
   if (!term)
     for (int j = t; j < nu; j += kWG) V.tu[j] = (float)U[(size_t)i * nu + j];
   dma_barrier();
-  lite_gemv_n(nx, nx, (const float*)(fp + I.oQ + (size_t)i * nx * nx), nx, V.tv, V.wv2, V.part, false);
+  // stage cost blocks from the epoch input packet (Q_N on its own)
+  const float* Zc = fp + I.oE + (size_t)(term ? 0 : i) * ep.stride + ep.Z;
+  const float* Qi = term ? (const float*)(fp + I.oQN) : Zc;
+  lite_gemv_n(nx, nx, Qi, term ? nx : ep.ld, V.tv, V.wv2, V.part, false);
   if (!term) {
-    lite_gemv_t(nu, nx, (const float*)(fp + I.oS + (size_t)i * nu * nx), nx, V.tu, V.wv, V.part);
+    const float* Si = Zc + (size_t)nx * ep.ld;   // S_i: rows nx.. of the cost block, columns 0..nx-1
+    lite_gemv_t(nu, nx, Si, ep.ld, V.tu, V.wv, V.part);
     for (int j = t; j < nx; j += kWG) V.wv2[j] += V.wv[j];
-    lite_gemv_n(nu, nu, (const float*)(fp + I.oR + (size_t)i * nu * nu), nu, V.tu, V.g, V.part, false);
-    lite_gemv_n(nu, nx, (const float*)(fp + I.oS + (size_t)i * nu * nx), nx, V.tv, V.g, V.part, true);
+    lite_gemv_n(nu, nu, Si + nx, ep.ld, V.tu, V.g, V.part, false);
+    lite_gemv_n(nu, nx, Si, ep.ld, V.tv, V.g, V.part, true);
     for (int j = t; j < nu; j += kWG) hx = fmax(hx, fabs((double)V.g[j]));
   }
   for (int j = t; j < nx; j += kWG) hx = fmax(hx, fabs((double)V.wv2[j]));
@@ -717,14 +912,6 @@ __device__ __attribute__((noinline)) double batch_hxi(const BInst* __restrict__ 
 // needs four workgroup barriers and a forward stage four (two of them inside
 // the product), about half of the general path's.
 
-// Barrier of one wave over its own LDS accesses: waits for its LDS
-// operations and keeps the compiler from moving LDS accesses across.
-__device__ __forceinline__ void wave_lds_sync() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
-  __builtin_amdgcn_wave_barrier();
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
 
 // Backward pass of box-row instances over [s, e) (semantics of
 // batch_backward<true>).
@@ -1872,14 +2059,15 @@ __global__ void __launch_bounds__(kWG) k_batch_rdyn(const BInst* __restrict__ in
   const int k = (int)blockIdx.x - row_off[c];
   if (k >= I.N) return;   // terminal row: uniform exit
   const int nx = I.nx, nu = I.nu, w = wave(), l = lane();
+  const EpLayout ep = ep_layout(nx, nu);
   const double* xk = dp + I.oX + (size_t)k * nx;
   const double* uk = dp + I.oU + (size_t)k * nu;
   double m = 0.0;
   for (int i = w; i < nx; i += 4) {
-    const float* Ar = fp + I.oA + ((size_t)k * nx + i) * nx;
-    const float* Br = fp + I.oB + ((size_t)k * nx + i) * nu;
+    // row i of [A_k | B_k] in the epoch input packet
+    const float* ABr = fp + I.oE + (size_t)k * ep.stride + ep.AB + (size_t)i * ep.ld;
     double a = 0.0;
-    for (int j = l; j < nx + nu; j += 64) a += j < nx ? (double)Ar[j] * xk[j] : (double)Br[j - nx] * uk[j - nx];
+    for (int j = l; j < nx + nu; j += 64) a += (double)ABr[j] * (j < nx ? xk[j] : uk[j - nx]);
     for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
     const double e = fabs(dp[I.oX + (size_t)(k + 1) * nx + i] - (double)fp[I.ob + (size_t)k * nx + i] - a);
     m = (e > m || e != e) ? e : m;
@@ -1965,8 +2153,40 @@ int batch_setup(const gsls_qp_desc* descs, int count, const gsls_settings* s, hi
     I.box = is_box(d, C, D, CN) ? 1 : 0;
     // general rows go through the GEMV helpers (at most 64 reduction rows)
     if (!I.box && (nc > (size_t)GSLS_MAX_NC || nf > (size_t)GSLS_MAX_NC)) return GSLS_ERR_DIM;
-    I.oA = pushf(d.A, N * nx * nx); I.oB = pushf(d.B, N * nx * nu); I.ob = pushf(d.b, N * nx);
-    I.oQ = pushf(d.Q, (N + 1) * nx * nx); I.oR = pushf(d.R, N * nu * nu); I.oS = pushf(d.S, N * nu * nx);
+    I.ob = pushf(d.b, N * nx);
+    {   // terminal cost, symmetric part
+      std::vector<double> QN(nx * nx, 0.0);
+      if (d.Q)
+        for (size_t r = 0; r < nx; ++r)
+          for (size_t c = 0; c < nx; ++c)
+            QN[r * nx + c] = 0.5 * (d.Q[(N * nx + r) * nx + c] + d.Q[(N * nx + c) * nx + r]);
+      I.oQN = pushf(QN.data(), nx * nx);
+    }
+    {   // epoch input packets
+      const EpLayout ep = ep_layout(d.nx, d.nu);
+      const size_t ld = ep.ld;
+      I.oE = reservef(N * (size_t)ep.stride);
+      for (size_t k = 0; k < N; ++k) {
+        float* e = fpool.data() + I.oE + k * ep.stride;
+        for (size_t r = 0; r < nx; ++r) {
+          for (size_t c = 0; c < nx; ++c) e[ep.AB + r * ld + c] = d.A ? (float)d.A[(k * nx + r) * nx + c] : 0.f;
+          for (size_t c = 0; c < nu; ++c) e[ep.AB + r * ld + nx + c] = d.B ? (float)d.B[(k * nx + r) * nu + c] : 0.f;
+        }
+        // cost block, symmetric part (only it enters the quadratic form)
+        auto cost = [&](size_t r, size_t c) -> double {
+          if (r < nx && c < nx) return d.Q ? d.Q[k * nx * nx + r * nx + c] : 0.0;
+          if (r >= nx && c >= nx) return d.R ? d.R[k * nu * nu + (r - nx) * nu + (c - nx)] : 0.0;
+          if (r >= nx) return d.S ? d.S[k * nu * nx + (r - nx) * nx + c] : 0.0;
+          return d.S ? d.S[k * nu * nx + (c - nx) * nx + r] : 0.0;
+        };
+        for (size_t r = 0; r < nxu; ++r)
+          for (size_t c = r; c < nxu; ++c) {
+            const float v = (float)(0.5 * (cost(r, c) + cost(c, r)));
+            e[ep.Z + r * ld + c] = v;
+            e[ep.Z + c * ld + r] = v;
+          }
+      }
+    }
     I.oq = pushf(d.q, (N + 1) * nx); I.orr = pushf(d.r, N * nu);
     if (!I.box) {
       std::vector<double> G(N * nc * nxu);

@@ -13,10 +13,28 @@ struct BInst {
   int N, nx, nu, nc, nf, box, m;
   int park_at;                                             // solo iterations before a gang takes over
   long long ogw, ogm;                                      // gang exchange words / transfer maps
-  long long oA, oB, ob, oQ, oR, oS, oq, orr, oG, oCN, ox0;  // float pool: problem
+  long long oE, oQN, ob, oq, orr, oG, oCN, ox0;           // float pool: problem
   long long oPk, okff;                                     // float pool: stage packets, feed-forward k
   long long ol, ou, oz, oy, ov, owp, oX, oU;                // double pool
 };
+
+// Per-stage input of the factor epoch in the float pool, laid out as the
+// epoch's LDS blocks so that it moves to LDS by linear DMA: [A_k | B_k]
+// (nx rows) and the symmetric part of the stage cost [[Q_k, S_k^T], [S_k, R_k]]
+// (nx + nu rows), both with the odd leading dimension ld = (nx + nu) | 1 and
+// zero padding, each block a multiple of 4 floats.
+struct EpLayout {
+  int ld, AB, Z, stride;
+};
+__host__ __device__ inline EpLayout ep_layout(int nx, int nu) {
+  EpLayout L;
+  const int nxu = nx + nu;
+  L.ld = nxu | 1;
+  L.AB = 0;
+  L.Z = (nx * L.ld + 3) & ~3;
+  L.stride = L.Z + ((nxu * L.ld + 3) & ~3);
+  return L;
+}
 
 struct BResult {
   int status, iterations, rho_updates, factorizations, restarted;

@@ -279,6 +279,7 @@ __global__ void __launch_bounds__(256) k_ws_features(const BInst* inst, const fl
   const BInst I = inst[c];
   const int k = rr - row_off[c];
   const int nx = I.nx, nu = I.nu, N = I.N;
+  const EpLayout ep = ep_layout(nx, nu);
   const float xm = (float)dp[I.ou], um = (float)dp[I.ou + nx];
   const float* x0 = fp + I.ox0;
   for (int j = l; j < 80; j += 64) xsh[w][j] = j < nx ? x0[j] : 0.f;
@@ -287,15 +288,16 @@ __global__ void __launch_bounds__(256) k_ws_features(const BInst* inst, const fl
     float d = 0.f;
     if (k < N) {
       if (j < nx) {
-        const float* Ar = fp + I.oA + ((long long)k * nx + j) * nx;
+        // row j of A_k in the epoch input packet ([A_k | B_k], leading dimension ep.ld)
+        const float* Ar = fp + I.oE + (long long)k * ep.stride + ep.AB + (long long)j * ep.ld;
         float s = 0.f;
         for (int cc = 0; cc < nx; ++cc) s += Ar[cc] * xsh[w][cc];
         d = (s - xsh[w][j]) / xm;
       } else if (j >= kXs && j < kXs + nu) {
         const int jj = j - kXs;
-        const float* Bk = fp + I.oB + (long long)k * nx * nu;
+        const float* Bk = fp + I.oE + (long long)k * ep.stride + ep.AB + nx;
         float s = 0.f;
-        for (int rr2 = 0; rr2 < nx; ++rr2) s += Bk[(long long)rr2 * nu + jj] * xsh[w][rr2];
+        for (int rr2 = 0; rr2 < nx; ++rr2) s += Bk[(long long)rr2 * ep.ld + jj] * xsh[w][rr2];
         d = s / xm;
       }
     }

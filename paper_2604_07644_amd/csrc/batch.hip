@@ -34,6 +34,7 @@ constexpr int kBatchMaxNxu = 96;
 constexpr int kGangMax = 32;          // workgroups per gang (6 kGangMax <= kWG: residual exchange)
 constexpr int kGangAuto = 32;
 constexpr double kParkShareAuto = 1.0;
+constexpr double kParkResid = 10.0;   // no hand-over once r_p, r_d <= kParkResid * tol
 
 __host__ __device__ inline int bodd(int x) { return x | 1; }
 
@@ -913,6 +914,24 @@ __device__ __attribute__((noinline)) double batch_hxi(const BInst* __restrict__ 
 // the product), about half of the general path's.
 
 
+// sum_q Gm[q][t] u[q] over q < nu <= QM, in order of q: every read issued
+// before the first product (clamped indices, terms past nu dropped).
+template <int QM>
+__device__ __forceinline__ float gam_dot(const LDS float* Gm, const LDS float* u, int nu, int t) {
+  float g[QM], v[QM];
+#pragma unroll
+  for (int q = 0; q < QM; ++q) {
+    const int qq = min(q, nu - 1);
+    g[q] = Gm[qq * nu + t];
+    v[q] = u[qq];
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int q = 0; q < QM; ++q)
+    if (q < nu) s += g[q] * v[q];
+  return s;
+}
+
 // Backward pass of box-row instances over [s, e) (semantics of
 // batch_backward<true>).
 __device__ __attribute__((noinline)) void box_backward(const BInst* __restrict__ Ip,
@@ -1002,8 +1021,17 @@ __device__ __attribute__((noinline)) void box_backward(const BInst* __restrict__
       if (t < nu) V.tu[t] = V.g2[nx + t] + cst * P[pk.fv + t];
       wave_lds_sync();
       if (t < nu) {
-        float kk = 0.f;
-        for (int q = 0; q < nu; ++q) kk += P[pk.Gam + q * nu + t] * V.tu[q];
+        const LDS float* Gm = P + pk.Gam;
+        float kk;
+        if (nu <= 4) kk = gam_dot<4>(Gm, V.tu, nu, t);
+        else if (nu <= 8) kk = gam_dot<8>(Gm, V.tu, nu, t);
+        else if (nu <= 16) kk = gam_dot<16>(Gm, V.tu, nu, t);
+        else if (nu <= 24) kk = gam_dot<24>(Gm, V.tu, nu, t);
+        else if (nu <= 32) kk = gam_dot<32>(Gm, V.tu, nu, t);
+        else {
+          kk = 0.f;
+          for (int q = 0; q < nu; ++q) kk += Gm[q * nu + t] * V.tu[q];
+        }
         kff[(size_t)i * nu + t] = -kk;
       }
     }
@@ -1461,7 +1489,10 @@ __device__ __attribute__((noinline)) int batch_iterate(const BInst* __restrict__
       return 4;
     }
     if (st) return st;
-    if (*it >= park_at) return 6;
+    // hand-over: not for an instance already close to the stopping test (a
+    // gang costs its members' waiting and a factor epoch; a few more solo
+    // iterations cost less)
+    if (*it >= park_at && !(o[0] <= kParkResid * a.tol && o[1] <= kParkResid * a.tol)) return 6;
   }
 }
 

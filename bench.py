@@ -38,13 +38,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "QP solves/s and ms/solve at 1e-5 residual; warm-start vs cold-start ADMM"
 
-# HBM bytes per launch of k_admm on the quadruped workload, from rocprofv3
+# HBM bytes per launch (averaged over the launches of a run), from rocprofv3
 # FETCH_SIZE and WRITE_SIZE runs scaled by the same counters on a 256 MiB
-# device copy (profiles/quadruped_k_admm_hbm_traffic.md).  Valid only for the
-# kernel source it was taken on: reported while the hash of that source matches.
-K_ADMM_TRAFFIC = {"src_sha256_16": "1958d4f523f0555c", "sources": ("iterate.hip", "dev_common.hpp", "solver.hpp"),
-                  "bytes_per_launch": 192072592.3}
-# The same for k_batch on the 512-instance batch (learned warm start).
+# device copy in the same process (profiles/*_hbm_traffic.md).  Valid only for
+# the kernel sources they were taken on: reported while the hash of those
+# sources matches.
+K_ADMM_TRAFFIC = {
+    "quadruped": {"src_sha256_16": "68ef4925e7ba47bb", "sources": ("iterate.hip", "dev_common.hpp", "solver.hpp"),
+                  "bytes_per_launch": 1.9077e8},
+    "humanoid": {"src_sha256_16": "68ef4925e7ba47bb", "sources": ("iterate.hip", "dev_common.hpp", "solver.hpp"),
+                 "bytes_per_launch": 1.4470e10},
+}
+# The same for k_batch on the 512-instance batch (learned warm start, predicted rho0).
 K_BATCH_TRAFFIC = {"src_sha256_16": "", "sources": ("batch.hip", "batch.hpp", "dev_common.hpp"),
                    "bytes_per_launch": None}
 
@@ -589,7 +594,7 @@ def main():
         "roofline": {"kernel": "k_admm (persistent ADMM iteration)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": kernel_traffic(K_ADMM_TRAFFIC) if args.workload == "quadruped" else None,
+                     "traffic": kernel_traffic(K_ADMM_TRAFFIC[args.workload]) if args.workload in K_ADMM_TRAFFIC else None,
                      "bytes_per_iteration": bytes_per_iter, "iterations_per_launch": mean_iters / launches,
                      "avg_launch_ms": ms_iter / launches},
     }

@@ -68,7 +68,7 @@ def tune_batch(probs, model_path, reps=2, log=print):
     stream = _device()
     b = gsls.Batch(probs, stream=stream)
     ws = gsls.WarmStart(path=model_path, stream=stream) if os.path.exists(model_path) else None
-    cands = [(1, 1.0)] + [(g, s) for g in (16, 24, 32) for s in (0.35, 0.5, 0.75, 1.0, 1.5)]
+    cands = [(1, 1.0)] + [(g, s) for g in (16, 24, 32) for s in (0.5, 0.75, 0.9, 1.0, 1.1, 1.25, 1.5)]
     results = []
     for g, s in cands:
         b.set_schedule(gang=g, park_share=s)

@@ -396,6 +396,75 @@ __device__ __forceinline__ mfma_f4 tile_mm(int k, const LDS float* A, int lda, c
   return acc;
 }
 
+// Two output tiles at once (tile_mm's scheme): their products alternate, so
+// the two accumulation chains overlap on the matrix core (a dependent
+// 16x16x4 product waits for its predecessor; two chains issue back to back).
+template <int KS, bool TA, bool TB>
+__device__ __forceinline__ void tile_mm2(int k, const LDS float* A, int lda, const LDS float* B, int ldb, int ic0,
+                                         int jc0, int ic1, int jc1, int q, mfma_f4& acc0, mfma_f4& acc1) {
+  const int sa = TA ? lda : 1, sb = TB ? 1 : ldb;
+  const LDS float* pa0 = TA ? A + q * lda + ic0 : A + ic0 * lda + q;
+  const LDS float* pb0 = TB ? B + jc0 * ldb + q : B + q * ldb + jc0;
+  const LDS float* pa1 = TA ? A + q * lda + ic1 : A + ic1 * lda + q;
+  const LDS float* pb1 = TB ? B + jc1 * ldb + q : B + q * ldb + jc1;
+  acc0 = mfma_f4{0.f, 0.f, 0.f, 0.f};
+  acc1 = mfma_f4{0.f, 0.f, 0.f, 0.f};
+  int k0 = 0;
+  for (; k0 + 4 * KS <= k; k0 += 4 * KS) {
+    float a0[KS], b0[KS], a1[KS], b1[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      a0[s] = pa0[(k0 + 4 * s) * sa];
+      b0[s] = pb0[(k0 + 4 * s) * sb];
+      a1[s] = pa1[(k0 + 4 * s) * sa];
+      b1[s] = pb1[(k0 + 4 * s) * sb];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[s], b0[s], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[s], b1[s], acc1, 0, 0, 0);
+    }
+  }
+  if (k0 < k) {
+    const int gfull = (k - k0) >> 2;
+    const int kp = k0 + 4 * gfull;
+    float a0[KS], b0[KS], a1[KS], b1[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+      if (s < gfull) {
+        a0[s] = pa0[(k0 + 4 * s) * sa];
+        b0[s] = pb0[(k0 + 4 * s) * sb];
+        a1[s] = pa1[(k0 + 4 * s) * sa];
+        b1[s] = pb1[(k0 + 4 * s) * sb];
+      }
+    float ap0 = 0.f, bp0 = 0.f, ap1 = 0.f, bp1 = 0.f;
+    if (kp < k) {
+      const int kc = min(kp + q, k - 1);
+      const bool in = kp + q < k;
+      const float va0 = TA ? A[kc * lda + ic0] : A[ic0 * lda + kc];
+      const float vb0 = TB ? B[jc0 * ldb + kc] : B[kc * ldb + jc0];
+      const float va1 = TA ? A[kc * lda + ic1] : A[ic1 * lda + kc];
+      const float vb1 = TB ? B[jc1 * ldb + kc] : B[kc * ldb + jc1];
+      ap0 = in ? va0 : 0.f;
+      bp0 = in ? vb0 : 0.f;
+      ap1 = in ? va1 : 0.f;
+      bp1 = in ? vb1 : 0.f;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+      if (s < gfull) {
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[s], b0[s], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[s], b1[s], acc1, 0, 0, 0);
+      }
+    if (kp < k) {
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ap0, bp0, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ap1, bp1, acc1, 0, 0, 0);
+    }
+  }
+}
+
 // C = alpha op(A) op(B) + beta C on the matrix cores for LDS operands with
 // k <= 96: 16 x 16 output tiles round-robin over the waves (tile_mm).  C may
 // share an array with A or B but not their elements.  Ends with a barrier.
@@ -405,10 +474,8 @@ __device__ __forceinline__ void mm_pl_k(int m, int n, int k, float alpha, const 
   const int l = lane(), w = wave();
   const int tn = (n + 15) >> 4, tm = (m + 15) >> 4;
   const int r16 = l & 15, q = l >> 4;
-  for (int t = w; t < tm * tn; t += 4) {
-    const int ti = t / tn, tj = t - ti * tn;
-    const int ic = min(ti * 16 + r16, m - 1), jc = min(tj * 16 + r16, n - 1);
-    const mfma_f4 acc = tile_mm<KS, TA, TB>(k, A, lda, B, ldb, ic, jc, q);
+  const int T = tm * tn;
+  auto store = [&](int ti, int tj, const mfma_f4& acc) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int ii = ti * 16 + 4 * q + r, jj = tj * 16 + r16;
@@ -417,6 +484,21 @@ __device__ __forceinline__ void mm_pl_k(int m, int n, int k, float alpha, const 
         if (beta != 0.f) v += beta * C[ii * ldc + jj];
         C[ii * ldc + jj] = v;
       }
+    }
+  };
+  // the wave's tiles w, w + 4, ... in pairs
+  for (int t = w; t < T; t += 8) {
+    const int ti0 = t / tn, tj0 = t - ti0 * tn;
+    const int ic0 = min(ti0 * 16 + r16, m - 1), jc0 = min(tj0 * 16 + r16, n - 1);
+    if (t + 4 < T) {
+      const int ti1 = (t + 4) / tn, tj1 = (t + 4) - ti1 * tn;
+      const int ic1 = min(ti1 * 16 + r16, m - 1), jc1 = min(tj1 * 16 + r16, n - 1);
+      mfma_f4 acc0, acc1;
+      tile_mm2<KS, TA, TB>(k, A, lda, B, ldb, ic0, jc0, ic1, jc1, q, acc0, acc1);
+      store(ti0, tj0, acc0);
+      store(ti1, tj1, acc1);
+    } else {
+      store(ti0, tj0, tile_mm<KS, TA, TB>(k, A, lda, B, ldb, ic0, jc0, q));
     }
   }
   __syncthreads();
@@ -442,15 +524,16 @@ __device__ __forceinline__ void mm_sym_pl_k(int n, int k, float alpha, const LDS
   const int tn = (n + 15) >> 4;
   const int r16 = l & 15, q = l >> 4;
   const int tiles = tn * (tn + 1) / 2;
-  for (int t = w; t < tiles; t += 4) {
-    int ti = 0, rem = t;   // upper tile t in row-major order of the upper triangle
+  auto tile_of = [&](int t, int& ti, int& tj) {   // upper tile t in row-major order of the upper triangle
+    ti = 0;
+    int rem = t;
     while (rem >= tn - ti) {
       rem -= tn - ti;
       ++ti;
     }
-    const int tj = ti + rem;
-    const int ic = min(ti * 16 + r16, n - 1), jc = min(tj * 16 + r16, n - 1);
-    const mfma_f4 acc = tile_mm<KS, TA, TB>(k, A, lda, B, ldb, ic, jc, q);
+    tj = ti + rem;
+  };
+  auto store = [&](int ti, int tj, const mfma_f4& acc) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int ii = ti * 16 + 4 * q + r, jj = tj * 16 + r16;
@@ -460,6 +543,22 @@ __device__ __forceinline__ void mm_sym_pl_k(int n, int k, float alpha, const LDS
         Cout[ii * ldo + jj] = v;
         Cout[jj * ldo + ii] = v;
       }
+    }
+  };
+  for (int t = w; t < tiles; t += 8) {
+    int ti0, tj0;
+    tile_of(t, ti0, tj0);
+    const int ic0 = min(ti0 * 16 + r16, n - 1), jc0 = min(tj0 * 16 + r16, n - 1);
+    if (t + 4 < tiles) {
+      int ti1, tj1;
+      tile_of(t + 4, ti1, tj1);
+      const int ic1 = min(ti1 * 16 + r16, n - 1), jc1 = min(tj1 * 16 + r16, n - 1);
+      mfma_f4 acc0, acc1;
+      tile_mm2<KS, TA, TB>(k, A, lda, B, ldb, ic0, jc0, ic1, jc1, q, acc0, acc1);
+      store(ti0, tj0, acc0);
+      store(ti1, tj1, acc1);
+    } else {
+      store(ti0, tj0, tile_mm<KS, TA, TB>(k, A, lda, B, ldb, ic0, jc0, q));
     }
   }
   __syncthreads();

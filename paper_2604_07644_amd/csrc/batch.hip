@@ -3,13 +3,15 @@
 //
 // A workgroup pulls whole instances from a device work queue (largest first)
 // and runs for each: the factor epoch (backward Riccati recursion with the
-// augmented costs of eq. (augmented_matrices); products on the FP32 matrix
-// cores, the nu x nu inverse in FP64), then ADMM iterations whose x-update
-// evaluates the cached affine map of eq. (gains_cache) (backward pass for p,
-// forward roll-out, as in the single-instance kernel but sequential over the
-// horizon inside the workgroup), the projection / dual update and the
+// augmented costs of eq. (augmented_matrices); stage inputs moved to LDS by
+// DMA, products on the FP32 matrix cores, the nu x nu inverse in FP64), then
+// ADMM iterations whose x-update evaluates the cached affine map of
+// eq. (gains_cache) (backward pass for p, forward roll-out, sequential over
+// the horizon inside the workgroup), the projection / dual update and the
 // residuals, with the OSQP-style rho adaptation re-running the epoch when rho
-// changes.  State, projection and residuals are FP64; after the first
+// changes.  An instance that outlasts its solo budget is handed to a gang of
+// workgroups that split its horizon into chunks combined by associative scans
+// (the gangs section below).  State, projection and residuals are FP64; after the first
 // iteration of each epoch the affine map is applied to the increment of
 // w = y - z with FP64 accumulation (see iterate.hip).
 //
@@ -1597,7 +1599,8 @@ __device__ __attribute__((noinline)) int batch_iterate(const BInst* __restrict__
 
 // ----------------------------------------------------------------- gangs
 // An instance that has not converged within its solo budget (park_at
-// iterations, a function of its size only) is continued by a gang of G
+// iterations, a function of its size only) and is not yet within kParkResid
+// of the stopping test is continued by a gang of G
 // workgroups that split its horizon into G chunks (Sec. IV-A: the affine maps
 // of the backward and forward recurrences are composed by associative scans
 // over the horizon).  Per iteration each member

@@ -258,7 +258,7 @@ __device__ __forceinline__ void lite_gemv_n(int m, int n, PM M, int ld, PX x, PY
 // over the lanes, rows over the waves) and y = M x (m <= 128 rows over the
 // lanes, columns over the waves).  Out-of-range terms load a clamped element
 // and are masked to zero.
-template <int R, bool TWO>
+template <int R, bool TWO, bool SYNC>
 __device__ __forceinline__ void fgemv_t_r(int m, int n, const LDS float* M, int ld, const LDS float* x, LDS float* y,
                                           LDS float* part) {
   const int lane = tid() & 63, w = tid() >> 6;
@@ -282,23 +282,24 @@ __device__ __forceinline__ void fgemv_t_r(int m, int n, const LDS float* M, int 
   if (TWO) part[w * 128 + 64 + lane] = s1;
   dma_barrier();
   for (int j = tid(); j < n; j += kWG) y[j] = part[j] + part[128 + j] + part[256 + j] + part[384 + j];
-  dma_barrier();
+  if (SYNC) dma_barrier();
 }
+template <bool SYNC = true>
 __device__ __forceinline__ void fgemv_t(int m, int n, const LDS float* M, int ld, const LDS float* x, LDS float* y,
                                         LDS float* part) {
   if (n > 64) {
-    if (m <= 16) fgemv_t_r<4, true>(m, n, M, ld, x, y, part);
-    else if (m <= 32) fgemv_t_r<8, true>(m, n, M, ld, x, y, part);
-    else if (m <= 64) fgemv_t_r<16, true>(m, n, M, ld, x, y, part);
-    else fgemv_t_r<24, true>(m, n, M, ld, x, y, part);
+    if (m <= 16) fgemv_t_r<4, true, SYNC>(m, n, M, ld, x, y, part);
+    else if (m <= 32) fgemv_t_r<8, true, SYNC>(m, n, M, ld, x, y, part);
+    else if (m <= 64) fgemv_t_r<16, true, SYNC>(m, n, M, ld, x, y, part);
+    else fgemv_t_r<24, true, SYNC>(m, n, M, ld, x, y, part);
   } else {
-    if (m <= 16) fgemv_t_r<4, false>(m, n, M, ld, x, y, part);
-    else if (m <= 32) fgemv_t_r<8, false>(m, n, M, ld, x, y, part);
-    else if (m <= 64) fgemv_t_r<16, false>(m, n, M, ld, x, y, part);
-    else fgemv_t_r<24, false>(m, n, M, ld, x, y, part);
+    if (m <= 16) fgemv_t_r<4, false, SYNC>(m, n, M, ld, x, y, part);
+    else if (m <= 32) fgemv_t_r<8, false, SYNC>(m, n, M, ld, x, y, part);
+    else if (m <= 64) fgemv_t_r<16, false, SYNC>(m, n, M, ld, x, y, part);
+    else fgemv_t_r<24, false, SYNC>(m, n, M, ld, x, y, part);
   }
 }
-template <int R, bool TWO>
+template <int R, bool TWO, bool SYNC>
 __device__ __forceinline__ void fgemv_n_r(int m, int n, const LDS float* M, int ld, const LDS float* x, LDS float* y,
                                           LDS float* part) {
   const int lane = tid() & 63, w = tid() >> 6;
@@ -322,20 +323,21 @@ __device__ __forceinline__ void fgemv_n_r(int m, int n, const LDS float* M, int 
   if (TWO) part[w * 128 + 64 + lane] = s1;
   dma_barrier();
   for (int i = tid(); i < m; i += kWG) y[i] = part[i] + part[128 + i] + part[256 + i] + part[384 + i];
-  dma_barrier();
+  if (SYNC) dma_barrier();
 }
+template <bool SYNC = true>
 __device__ __forceinline__ void fgemv_n(int m, int n, const LDS float* M, int ld, const LDS float* x, LDS float* y,
                                         LDS float* part) {
   if (m > 64) {
-    if (n <= 16) fgemv_n_r<4, true>(m, n, M, ld, x, y, part);
-    else if (n <= 32) fgemv_n_r<8, true>(m, n, M, ld, x, y, part);
-    else if (n <= 64) fgemv_n_r<16, true>(m, n, M, ld, x, y, part);
-    else fgemv_n_r<24, true>(m, n, M, ld, x, y, part);
+    if (n <= 16) fgemv_n_r<4, true, SYNC>(m, n, M, ld, x, y, part);
+    else if (n <= 32) fgemv_n_r<8, true, SYNC>(m, n, M, ld, x, y, part);
+    else if (n <= 64) fgemv_n_r<16, true, SYNC>(m, n, M, ld, x, y, part);
+    else fgemv_n_r<24, true, SYNC>(m, n, M, ld, x, y, part);
   } else {
-    if (n <= 16) fgemv_n_r<4, false>(m, n, M, ld, x, y, part);
-    else if (n <= 32) fgemv_n_r<8, false>(m, n, M, ld, x, y, part);
-    else if (n <= 64) fgemv_n_r<16, false>(m, n, M, ld, x, y, part);
-    else fgemv_n_r<24, false>(m, n, M, ld, x, y, part);
+    if (n <= 16) fgemv_n_r<4, false, SYNC>(m, n, M, ld, x, y, part);
+    else if (n <= 32) fgemv_n_r<8, false, SYNC>(m, n, M, ld, x, y, part);
+    else if (n <= 64) fgemv_n_r<16, false, SYNC>(m, n, M, ld, x, y, part);
+    else fgemv_n_r<24, false, SYNC>(m, n, M, ld, x, y, part);
   }
 }
 
@@ -583,7 +585,10 @@ __device__ __forceinline__ void lds_dma_issue(const float* src, int n, LDS float
   src = uniform_ptr(src);
   n = __builtin_amdgcn_readfirstlane(n);
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)src, (short)0, n * 4, 0x00020000);
-  const int w = (int)tid() >> 6;
+  // the LDS destination (M0) computed on the scalar unit: a wave-uniform
+  // wave index, so no vector -> scalar round trip per copy
+  dst = uniform_lds(dst);
+  const int w = __builtin_amdgcn_readfirstlane((int)tid() >> 6);
   const int vo = (int)tid() * 16;
 #pragma unroll
   for (int q = 0; q < 10; ++q)
@@ -822,7 +827,10 @@ __device__ __forceinline__ void pk_dma_issue(const float* src, int n, LDS float*
   src = uniform_ptr(src);
   n = __builtin_amdgcn_readfirstlane(n);
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)src, (short)0, n * 4, 0x00020000);
-  const int w = (int)tid() >> 6;
+  // the LDS destination (M0) computed on the scalar unit: a wave-uniform
+  // wave index, so no vector -> scalar round trip per copy
+  dst = uniform_lds(dst);
+  const int w = __builtin_amdgcn_readfirstlane((int)tid() >> 6);
   const int vo = (int)tid() * 16;
 #pragma unroll
   for (int q = 0; q < kPkVec; ++q)
@@ -1116,10 +1124,16 @@ __device__ __attribute__((noinline)) void box_backward(const BInst* __restrict__
     // F^T [p; r_hat] over all four waves (ends with a barrier); then thread j
     // forms p_k[j] and, in wave 0, k_k = -Gamma^T (B^T p + r_hat + cst fv)
     // with only that wave's own LDS ordering
-    fgemv_t(nxu, fold ? nx : nxu, (const LDS float*)(P + pk.F), pk.ldF, V.xz, V.g2, V.part);
+    // (no closing barrier: thread j reads only its own output entry below, and
+    // wave 0 sums the input rows' partial sums itself; the stage-end barrier
+    // orders everything else)
+    fgemv_t<false>(nxu, fold ? nx : nxu, (const LDS float*)(P + pk.F), pk.ldF, V.xz, V.g2, V.part);
     if (t < nx) V.g[t] = V.g2[t] + V.wv2[t];
     if (!fold && w == 0) {
-      if (t < nu) V.tu[t] = V.g2[nx + t] + cst * P[pk.fv + t];
+      if (t < nu) {
+        const int j = nx + t;
+        V.tu[t] = V.part[j] + V.part[128 + j] + V.part[256 + j] + V.part[384 + j] + cst * P[pk.fv + t];
+      }
       wave_lds_sync();
       if (t < nu) {
         const LDS float* Gm = P + pk.Gam;
@@ -1185,7 +1199,7 @@ __device__ __attribute__((noinline)) void box_forward(const BInst* __restrict__ 
         if (t < nu) kf = kff[(size_t)(i + 1) * nu + t];
       }
       dma_barrier();
-      fgemv_n(nx, nxu, (const LDS float*)(P + pk.F), pk.ldF, xa, V.tu, V.part);
+      fgemv_n<false>(nx, nxu, (const LDS float*)(P + pk.F), pk.ldF, xa, V.tu, V.part);   // own entries only below
       if (t < nx) xa[t] = V.tu[t] + cst * P[pk.b + t];
       pk_dma_wait();
       dma_barrier();
@@ -1212,7 +1226,7 @@ __device__ __attribute__((noinline)) void box_forward(const BInst* __restrict__ 
       sv = vacc[gr]; sy = ys[gr]; sz = zs[gr]; sl = ls[gr]; su = us[gr];
     }
     if (t < nx) sX = X[(size_t)s * nx + t];
-    if (s < N && t < nu) sU = U[(size_t)s * nu + t];
+    if (s < N && t >= nx && t < nxu) sU = U[(size_t)s * nu + (t - nx)];   // u entry of thread t = nx + j
   }
   float sK = (s < N && t < nu) ? kff[(size_t)s * nu + t] : 0.f;
   pk_dma_wait();
@@ -1234,7 +1248,7 @@ __device__ __attribute__((noinline)) void box_forward(const BInst* __restrict__ 
         nv = vacc[gr]; ny = ys[gr]; nz = zs[gr]; nl = ls[gr]; nu_ = us[gr];
       }
       if (t < nx) nX = X[(size_t)(i + 1) * nx + t];
-      if (i + 1 < N && t < nu) nU = U[(size_t)(i + 1) * nu + t];
+      if (i + 1 < N && t >= nx && t < nxu) nU = U[(size_t)(i + 1) * nu + (t - nx)];
     }
     if (t < nx) X[(size_t)i * nx + t] = full ? (double)xa[t] : sX + (double)xa[t];
     mark(6);
@@ -1242,9 +1256,10 @@ __device__ __attribute__((noinline)) void box_forward(const BInst* __restrict__ 
       dma_barrier();
       mark(7);
       // F [x; k] = [Abar x + B k; K x + k] over all four waves (ends with a barrier)
-      fgemv_n(nxu, nxu, (const LDS float*)(P + pk.F), pk.ldF, xa, V.tu, V.part);
+      // (no closing barrier: every reader below reads its own entry of V.tu)
+      fgemv_n<false>(nxu, nxu, (const LDS float*)(P + pk.F), pk.ldF, xa, V.tu, V.part);
       mark(8);
-      if (t < nu) U[(size_t)i * nu + t] = full ? (double)V.tu[nx + t] : sU + (double)V.tu[nx + t];
+      if (t >= nx && t < nxu) U[(size_t)i * nu + (t - nx)] = full ? (double)V.tu[t] : sU + (double)V.tu[t];
     }
     mark(9);
     if (t < nr) {

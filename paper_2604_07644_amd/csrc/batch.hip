@@ -1093,37 +1093,44 @@ __device__ __attribute__((noinline)) void box_backward(const BInst* __restrict__
     const size_t gr = (size_t)(e - 1) * nc + t;
     ry = ys[gr]; rz = zs[gr]; rw = wprev[gr];
   }
+  // r_k of input row t (the packet holds the same values; reading it from the
+  // problem data lets the input vector of a stage be formed before its packet
+  // has arrived)
+  const float* rk = fp + I.orr;
+  auto dw_of = [&](double y_, double z_, double w_) {
+    const double wt = y_ - z_;
+    return (float)(full ? wt : wt - w_);
+  };
+  // input vector [p; r_hat] of the first stage, own entries
+  if (t < nx) V.xz[t] = V.g[t];
+  else if (t < nc) V.xz[t] = cst * rk[(size_t)(e - 1) * nu + (t - nx)] + fr * dw_of(ry, rz, rw);
   pk_dma_wait();
   dma_barrier();
   int cb = 0;
   for (int i = e - 1; i >= s; --i) {
     LDS float* P = V.buf(cb);
     double ny = 0.0, nz = 0.0, nw = 0.0;
+    float nr = 0.f;
     if (i > s) {
       pk_dma_issue(pkt + (size_t)(i - 1) * pst, pst, V.buf(cb ^ 1));
       if (t < nc) {
         const size_t gr = (size_t)(i - 1) * nc + t;
         ny = ys[gr]; nz = zs[gr]; nw = wprev[gr];
       }
+      if (t >= nx && t < nc) nr = rk[(size_t)(i - 1) * nu + (t - nx)];
     }
     mark(0);
-    // row t of the stage: state row t < nx, input row t - nx
+    // row t of the stage: state row t < nx (its own terms, read back by the
+    // same thread below), input row t - nx (already in the input vector)
     if (t < nc) {
       const double wt = ry - rz;
-      const float dw = (float)(full ? wt : wt - rw);
       if (!fold) wprev[(size_t)i * nc + t] = wt;
-      if (t < nx) {
-        V.xz[t] = V.g[t];
-        V.wv2[t] = cst * (P[pk.q + t] + P[pk.ev + t]) + fr * dw;
-      } else {
-        V.xz[t] = cst * P[pk.r + (t - nx)] + fr * dw;
-      }
+      if (t < nx) V.wv2[t] = cst * (P[pk.q + t] + P[pk.ev + t]) + fr * dw_of(ry, rz, rw);
     }
-    dma_barrier();
     mark(3);
-    // F^T [p; r_hat] over all four waves (ends with a barrier); then thread j
-    // forms p_k[j] and, in wave 0, k_k = -Gamma^T (B^T p + r_hat + cst fv)
-    // with only that wave's own LDS ordering
+    // F^T [p; r_hat] over all four waves; then thread j forms p_k[j] and, in
+    // wave 0, k_k = -Gamma^T (B^T p + r_hat + cst fv) with only that wave's
+    // own LDS ordering
     // (no closing barrier: thread j reads only its own output entry below, and
     // wave 0 sums the input rows' partial sums itself; the stage-end barrier
     // orders everything else)
@@ -1149,6 +1156,12 @@ __device__ __attribute__((noinline)) void box_backward(const BInst* __restrict__
         }
         kff[(size_t)i * nu + t] = -kk;
       }
+    }
+    // input vector of the next stage, own entries (every read of V.xz in this
+    // stage precedes the GEMV's internal barrier)
+    if (i > s) {
+      if (t < nx) V.xz[t] = V.g[t];
+      else if (t < nc) V.xz[t] = cst * nr + fr * dw_of(ny, nz, nw);
     }
     mark(4);
     ry = ny; rz = nz; rw = nw;
@@ -1188,19 +1201,20 @@ __device__ __attribute__((noinline)) void box_forward(const BInst* __restrict__ 
   if (fold) {
     if (s < e) pk_dma_issue(pkt + (size_t)s * pst, pst, V.buf0);
     float kf = (s < e && t < nu) ? kff[(size_t)s * nu + t] : 0.f;
+    if (s < e && t < nu) xa[nx + t] = kf;   // the first stage's feed-forward entry
     pk_dma_wait();
     dma_barrier();
     int cb = 0;
     for (int i = s; i < e; ++i) {
       LDS float* P = V.buf(cb);
-      if (t < nu) xa[nx + t] = kf;
       if (i + 1 < e) {
         pk_dma_issue(pkt + (size_t)(i + 1) * pst, pst, V.buf(cb ^ 1));
         if (t < nu) kf = kff[(size_t)(i + 1) * nu + t];
       }
-      dma_barrier();
-      fgemv_n<false>(nx, nxu, (const LDS float*)(P + pk.F), pk.ldF, xa, V.tu, V.part);   // own entries only below
+      // [x; k] complete since the previous barrier; own entries only below
+      fgemv_n<false>(nx, nxu, (const LDS float*)(P + pk.F), pk.ldF, xa, V.tu, V.part);
       if (t < nx) xa[t] = V.tu[t] + cst * P[pk.b + t];
+      if (i + 1 < e && t < nu) xa[nx + t] = kf;   // the next stage's feed-forward entry
       pk_dma_wait();
       dma_barrier();
       cb ^= 1;
@@ -1229,6 +1243,7 @@ __device__ __attribute__((noinline)) void box_forward(const BInst* __restrict__ 
     if (s < N && t >= nx && t < nxu) sU = U[(size_t)s * nu + (t - nx)];   // u entry of thread t = nx + j
   }
   float sK = (s < N && t < nu) ? kff[(size_t)s * nu + t] : 0.f;
+  if (s < N && t < nu) xa[nx + t] = sK;   // the first stage's feed-forward entry
   pk_dma_wait();
   dma_barrier();
   int cb = 0;
@@ -1237,7 +1252,6 @@ __device__ __attribute__((noinline)) void box_forward(const BInst* __restrict__ 
     const int nr = term ? nf : nc;
     LDS float* P = V.buf(cb);
     double nv = 0.0, ny = 0.0, nz = 0.0, nl = 0.0, nu_ = 0.0, nX = 0.0, nU = 0.0;
-    if (!term && t < nu) xa[nx + t] = sK;
     if (i + 1 < e) pk_dma_issue(pkt + (size_t)(i + 1) * pst, pst, V.buf(cb ^ 1));
     float nK = 0.f;
     if (i + 1 < N && i + 1 <= last && t < nu) nK = kff[(size_t)(i + 1) * nu + t];
@@ -1253,7 +1267,7 @@ __device__ __attribute__((noinline)) void box_forward(const BInst* __restrict__ 
     if (t < nx) X[(size_t)i * nx + t] = full ? (double)xa[t] : sX + (double)xa[t];
     mark(6);
     if (!term) {
-      dma_barrier();
+      // [x; k] is complete since the previous barrier
       mark(7);
       // F [x; k] = [Abar x + B k; K x + k] over all four waves (ends with a barrier)
       // (no closing barrier: every reader below reads its own entry of V.tu)
@@ -1289,6 +1303,9 @@ __device__ __attribute__((noinline)) void box_forward(const BInst* __restrict__ 
       dma_barrier();
       break;
     }
+    // the next stage's feed-forward entry (every read of xa[nx..] in this
+    // stage precedes the GEMV's internal barrier)
+    if (i + 1 < N && t < nu) xa[nx + t] = nK;
     sv = nv; sy = ny; sz = nz; sl = nl; su = nu_; sX = nX; sU = nU; sK = nK;
     pk_dma_wait();
     dma_barrier();

@@ -258,8 +258,8 @@ __device__ __forceinline__ void lite_gemv_n(int m, int n, PM M, int ld, PX x, PY
 // over the lanes, rows over the waves) and y = M x (m <= 128 rows over the
 // lanes, columns over the waves).  Out-of-range terms load a clamped element
 // and are masked to zero.
-template <int R, bool TWO, bool SYNC>
-__device__ __forceinline__ void fgemv_t_r(int m, int n, const LDS float* M, int ld, const LDS float* x, LDS float* y,
+template <int R, bool TWO, bool SYNC, typename PM>
+__device__ __forceinline__ void fgemv_t_r(int m, int n, PM M, int ld, const LDS float* x, LDS float* y,
                                           LDS float* part) {
   const int lane = tid() & 63, w = tid() >> 6;
   const int j0 = min(lane, n - 1), j1 = min(64 + lane, n - 1);
@@ -284,8 +284,8 @@ __device__ __forceinline__ void fgemv_t_r(int m, int n, const LDS float* M, int 
   for (int j = tid(); j < n; j += kWG) y[j] = part[j] + part[128 + j] + part[256 + j] + part[384 + j];
   if (SYNC) dma_barrier();
 }
-template <bool SYNC = true>
-__device__ __forceinline__ void fgemv_t(int m, int n, const LDS float* M, int ld, const LDS float* x, LDS float* y,
+template <bool SYNC = true, typename PM>
+__device__ __forceinline__ void fgemv_t(int m, int n, PM M, int ld, const LDS float* x, LDS float* y,
                                         LDS float* part) {
   if (n > 64) {
     if (m <= 16) fgemv_t_r<4, true, SYNC>(m, n, M, ld, x, y, part);
@@ -299,8 +299,8 @@ __device__ __forceinline__ void fgemv_t(int m, int n, const LDS float* M, int ld
     else fgemv_t_r<24, false, SYNC>(m, n, M, ld, x, y, part);
   }
 }
-template <int R, bool TWO, bool SYNC>
-__device__ __forceinline__ void fgemv_n_r(int m, int n, const LDS float* M, int ld, const LDS float* x, LDS float* y,
+template <int R, bool TWO, bool SYNC, typename PM>
+__device__ __forceinline__ void fgemv_n_r(int m, int n, PM M, int ld, const LDS float* x, LDS float* y,
                                           LDS float* part) {
   const int lane = tid() & 63, w = tid() >> 6;
   const int i0 = min(lane, m - 1), i1 = min(64 + lane, m - 1);
@@ -325,8 +325,8 @@ __device__ __forceinline__ void fgemv_n_r(int m, int n, const LDS float* M, int 
   for (int i = tid(); i < m; i += kWG) y[i] = part[i] + part[128 + i] + part[256 + i] + part[384 + i];
   if (SYNC) dma_barrier();
 }
-template <bool SYNC = true>
-__device__ __forceinline__ void fgemv_n(int m, int n, const LDS float* M, int ld, const LDS float* x, LDS float* y,
+template <bool SYNC = true, typename PM>
+__device__ __forceinline__ void fgemv_n(int m, int n, PM M, int ld, const LDS float* x, LDS float* y,
                                         LDS float* part) {
   if (m > 64) {
     if (n <= 16) fgemv_n_r<4, true, SYNC>(m, n, M, ld, x, y, part);
@@ -1899,7 +1899,9 @@ __device__ __attribute__((noinline)) void gang_run(const BInst* __restrict__ Ip,
           if (!g_fetch(words + gl.bwd + ((size_t)d * G + pr) * nx, stamp, V.g2, nx, &a.sync->abort, &s_flag)) {
             ok = false; break;
           }
-          lite_gemv_t(nx, nx, maps + ((size_t)d * G + r) * xx, nx, V.g2, V.tv, V.part);
+          // map from global memory: every load of a thread issued before its
+          // first product (one memory latency per level)
+          fgemv_t(nx, nx, maps + ((size_t)d * G + r) * xx, nx, V.g2, V.tv, V.part);
           for (int j = t; j < nx; j += kWG) V.g[j] += V.tv[j];
           dma_barrier();
         }
@@ -1930,7 +1932,9 @@ __device__ __attribute__((noinline)) void gang_run(const BInst* __restrict__ Ip,
           if (!g_fetch(words + gl.fwd + ((size_t)d * G + pr) * nx, stamp, V.g2, nx, &a.sync->abort, &s_flag)) {
             ok = false; break;
           }
-          lite_gemv_n(nx, nx, maps + ((size_t)d * G + pr + 1) * xx, nx, V.g2, V.g, V.part, true);
+          fgemv_n(nx, nx, maps + ((size_t)d * G + pr + 1) * xx, nx, V.g2, V.tv, V.part);
+          for (int j = t; j < nx; j += kWG) V.g[j] += V.tv[j];
+          dma_barrier();
         }
         g_publish(words + gl.fwd + ((size_t)(d + 1) * G + r) * nx, stamp, V.g, nx);
       }

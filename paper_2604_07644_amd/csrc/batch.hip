@@ -1885,12 +1885,10 @@ __device__ __attribute__((noinline)) void gang_run(const BInst* __restrict__ Ip,
     const bool full = first || (a.refresh > 0 && it % a.refresh == 0);
     const float cst = full ? 1.f : 0.f;
     const bool sigma_it = a.adaptive && ((it - it0) % a.sigma == 0) && it < limit;
-    // ---- backward: fold, doubling, re-run from the exact entry
-    if (r == G - 1) {
-      stage_backward<BOX>(Ip, ag, (float)rho, full, base, s, e, false);
-    } else if (r > 0) {
-      stage_backward<BOX>(Ip, ag, (float)rho, full, base, s, e, true);
-    }
+    // ---- backward: fold, doubling, re-run from the exact entry.  The last
+    // member's entry is exact already; it folds too (its fold is its chunk's
+    // exact p_s) and re-runs after publishing, off the doubling's critical path
+    if (r > 0) stage_backward<BOX>(Ip, ag, (float)rho, full, base, s, e, true);
     if (r > 0) {
       g_publish(words + gl.bwd + (size_t)r * nx, stamp, V.g, nx);
       for (int d = 0; d < nlev; ++d) {
@@ -1913,15 +1911,13 @@ __device__ __attribute__((noinline)) void gang_run(const BInst* __restrict__ Ip,
       if (!g_fetch(words + gl.bwd + ((size_t)nlev * G + r + 1) * nx, stamp, V.g, nx, &a.sync->abort, &s_flag)) {
         ok = false; break;
       }
-      stage_backward<BOX>(Ip, ag, (float)rho, full, base, s, e, false);
     }
-    // ---- forward: fold, doubling, re-run with projection and residuals
+    stage_backward<BOX>(Ip, ag, (float)rho, full, base, s, e, false);   // (the last chunk starts from p_N)
+    // ---- forward: fold, doubling, re-run with projection and residuals.
+    // The first member's entry x_0 is exact: its fold is its chunk's exact
+    // x_e, published before its re-run
     for (int j = t; j < nx; j += kWG) V.xz[j] = (r == 0) ? cst * a.fp[I.ox0 + j] : 0.f;
-    if (r == 0) {
-      stage_forward<BOX>(Ip, ag, rho, full, sigma_it, base, s, e, false);
-    } else if (r < G - 1) {
-      stage_forward<BOX>(Ip, ag, rho, full, sigma_it, base, s, e, true);
-    }
+    if (r < G - 1) stage_forward<BOX>(Ip, ag, rho, full, sigma_it, base, s, e, true);
     if (r < G - 1) {
       for (int j = t; j < nx; j += kWG) V.g[j] = V.xz[j];
       dma_barrier();
@@ -1944,8 +1940,10 @@ __device__ __attribute__((noinline)) void gang_run(const BInst* __restrict__ Ip,
       if (!g_fetch(words + gl.fwd + ((size_t)nlev * G + r - 1) * nx, stamp, V.xz, nx, &a.sync->abort, &s_flag)) {
         ok = false; break;
       }
-      stage_forward<BOX>(Ip, ag, rho, full, sigma_it, base, s, e, false);
+    } else {
+      for (int j = t; j < nx; j += kWG) V.xz[j] = cst * a.fp[I.ox0 + j];
     }
+    stage_forward<BOX>(Ip, ag, rho, full, sigma_it, base, s, e, false);
     first = false;
     // ---- residual terms of the whole instance (same order on every member)
     LDS double* out = V.red + kWG;

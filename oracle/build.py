@@ -34,6 +34,18 @@ def build_native(outdir, verbose=False) -> str:
     return out
 
 
+def build_sanitized(outdir, verbose=False) -> str:
+    """AddressSanitizer + UndefinedBehaviorSanitizer build into outdir (the
+    tests load it in a child process with the sanitizer runtimes preloaded)."""
+    out = os.path.join(outdir, "_oracle_san.so")
+    cmd = ["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", out, SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
     sys.exit(0)

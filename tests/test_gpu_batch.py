@@ -139,3 +139,30 @@ def test_gang_warm_restart_and_rho_changes():
         assert r4["rho_updates"] >= 1 or r4["factorizations"] >= 2
         ref = oracle.qp_solve(p, rho=1.0, tol=1e-10)
         assert _err(out[4][1][i], ref["X"]) <= max(1e-4, 3 * _err(out[1][1][i], ref["X"]))
+
+
+@pytest.mark.parametrize("nu", [6, 14, 28, 32])
+def test_gain_of_every_control_size_class(nu):
+    """The factor epoch forms Gamma = Z_uu^{-1} in one wave, in register
+    layouts for nu <= 4, 8, 12, 16, 20 and 32 (the benchmark batch reaches the
+    4, 12 and 20 ones); the others against the oracle here, box and general
+    rows.  Larger control dimensions are refused at set-up."""
+    probs = [W.box_lq(N=12, nx=8, nu=nu, cfg_id=7, instance_id=nu),
+             W.random_small(10, 6, nu, 5, 2, seed=60 + nu)]
+    b = gsls.Batch(probs)
+    res, _ = b.solve(tol=1e-6)
+    for i, p in enumerate(probs):
+        assert res[i]["status"] == gsls.SOLVED, (i, res[i])
+        g = b.get(i)
+        ref = oracle.qp_solve(p, rho=1.0, tol=1e-10)
+        at_tol = oracle.qp_solve(p, rho=1.0, tol=1e-6)
+        for key in ("X", "U"):
+            bar = max(1e-4, 3 * _err(at_tol[key], ref[key]))
+            assert _err(g[key], ref[key]) <= bar, (i, nu, key, _err(g[key], ref[key]), bar)
+    b.close()
+
+
+def test_control_dimension_beyond_32_is_refused():
+    with pytest.raises(gsls.GslsError) as ei:
+        gsls.Batch([W.box_lq(N=12, nx=8, nu=40)])
+    assert ei.value.code == gsls.ERR_DIM

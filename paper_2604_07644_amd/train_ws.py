@@ -99,12 +99,10 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--workers", type=int, default=12)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--stream", action="store_true",
+                    help="generate and solve 512 instances at a time in this process (large training sets)")
     ap.add_argument("--out", default=os.path.join(ROOT, "paper_2604_07644_amd", "data", "ws_box.bin"))
     args = ap.parse_args()
-
-    t0 = time.perf_counter()
-    probs = generate_problems(args.instances, workers=args.workers)
-    print(f"generated {len(probs)} problems in {time.perf_counter() - t0:.1f} s", flush=True)
 
     import torch
     from paper_2604_07644_amd import gsls, workloads as W
@@ -112,8 +110,26 @@ def main():
                         stream=torch.cuda.current_stream().cuda_stream)
     log = lambda s: print(s, flush=True)  # noqa: E731
     t1 = time.perf_counter()
-    X, T, M, solved = build_dataset(ws, probs, log=log)
-    del probs
+    if args.stream:
+        # generate (worker processes), solve and keep only the device rows,
+        # 512 instances at a time: host memory holds one batch's problem data
+        Xs, Ts, Ms, solved = [], [], [], 0
+        for i in range(0, args.instances, 512):
+            probs = generate_problems(min(512, args.instances - i), first=TRAIN_FIRST_ID + i,
+                                      workers=args.workers)
+            X, T, M, n = build_dataset(ws, probs, log=log)
+            Xs.append(X); Ts.append(T); Ms.append(M)
+            solved += n
+            del probs
+            log(f"streamed {i + 512} instances in {time.perf_counter() - t1:.1f} s")
+        X, T, M = torch.cat(Xs), torch.cat(Ts), torch.cat(Ms)
+        del Xs, Ts, Ms
+    else:
+        t0 = time.perf_counter()
+        probs = generate_problems(args.instances, workers=args.workers)
+        print(f"generated {len(probs)} problems in {time.perf_counter() - t0:.1f} s", flush=True)
+        X, T, M, solved = build_dataset(ws, probs, log=log)
+        del probs
     print(f"dataset: {solved} solved instances, {X.shape[0]} rows in {time.perf_counter() - t1:.1f} s",
           flush=True)
     t2 = time.perf_counter()

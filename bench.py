@@ -563,6 +563,7 @@ def main():
     q.close()
 
     ok = all(r["status"] == gsls.SOLVED for r in res)
+    one_wave = tuple(lay) == (1, 1, 1, p.N)
     iters = [r["iterations"] for r in res]
     ms_iter = float(np.mean([r["ms_iterate"] for r in res]))
     ms_fact = float(np.mean([r["ms_factor"] for r in res]))
@@ -598,9 +599,33 @@ def main():
                      "bytes_per_iteration": bytes_per_iter, "iterations_per_launch": mean_iters / launches,
                      "avg_launch_ms": ms_iter / launches},
     }
+    if one_wave:
+        # the one-wavefront path: the whole solve is one launch of one wave,
+        # bound by its own FP64 issue rate, not by memory
+        ms_kernel = float(np.mean([r["ms_total"] for r in res]))
+        flops = tiny_flops_per_iteration(p) * mean_iters
+        achieved = flops / (ms_kernel * 1e-3) / 1e9
+        one_simd = FP64_VECTOR_PEAK_GFS / 1024.0
+        line["dtype"] = "f64"
+        line["roofline"] = {"kernel": "k_tiny (one-wavefront solve)", "bound": "alu", "achieved": achieved,
+                            "peak": FP64_VECTOR_PEAK_GFS, "unit": "GFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_GFS,
+                            "peak_one_simd": one_simd, "frac_one_simd": achieved / one_simd, "traffic": None,
+                            "flops_per_iteration": tiny_flops_per_iteration(p), "avg_launch_ms": ms_kernel}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_budget, tol)
     print(json.dumps(line), flush=True)
+
+
+FP64_VECTOR_PEAK_GFS = 78.6e3   # published FP64 vector rate: 256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz
+
+
+def tiny_flops_per_iteration(p):
+    """Algorithmic FP64 flops of one ADMM iteration of the Riccati-form x-update
+    (per stage: linear terms, feed-forward solve, backward and forward
+    recursions, constraint map, projection, dual residual)."""
+    nx, nu, nc = p.nx, p.nu, p.nc
+    per_stage = 6 * nx * nx + 8 * nx * nu + 2 * nu * nu + 6 * nc * (nx + nu) + 4 * nc
+    return p.N * per_stage + 4 * p.nf * nx
 
 
 if __name__ == "__main__":

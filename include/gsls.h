@@ -97,7 +97,10 @@ typedef struct gsls_settings {
   int32_t chunks_epoch;  /* horizon chunks for the factor scan (0 = auto:     [0]
                             one stage per chunk, at most 256 chunks) */
   int32_t chunks_iter;   /* horizon chunks (workgroups) for the iteration      [0]
-                            scans (0 = auto: one stage per workgroup, at most 256) */
+                            scans (0 = auto: one stage per workgroup, at most 256;
+                            with chunks_epoch also 0, problems with nx, nu <= 4,
+                            nc, nf <= 8 and N <= 63 are solved whole by one
+                            wavefront in FP64, whatever the precision) */
   int32_t refresh;       /* mixed precision: the x-update is evaluated on the  [0]
                             increment of w = y - z and accumulated in FP64, in
                             full after each factor epoch and, if refresh > 0,
@@ -185,7 +188,12 @@ void gsls_qp_free(gsls_qp* h);
  * exchange, [7] forward fix-up + projection + dual update, [8] residual
  * reduction; the counters are then cleared.  layout4 (nullable) receives the
  * factor-scan chunk count, the iteration chunk (workgroup) count, whether the
- * chunk operators are LDS-resident, and the largest chunk length. */
+ * chunk operators are LDS-resident, and the largest chunk length.
+ * Tiny problems (nx, nu <= 4, nc, nf <= 8, N <= 63, both chunk settings 0) run
+ * the whole solve in one wavefront in FP64: layout4 is then {1, 1, 1, N} and
+ * cycles16 holds [0] solves, [1] shader cycles of the data load, [2] of the
+ * factors, [3] of the iterations, [4] 100 MHz ticks of factors + iterations,
+ * [5] factors, [6] iterations, summed over the solves since the last read. */
 int gsls_debug_phase_cycles(gsls_qp* h, int32_t enable, double* cycles16, int32_t* layout4);
 
 /* ----------------------------------------------------------------- SLS ---

@@ -12,7 +12,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgsls.so")
-SOURCES = ["api.hip", "epoch.hip", "iterate.hip", "sls.hip", "batch.hip", "mlp.hip", "models.hip"]
+SOURCES = ["api.hip", "epoch.hip", "iterate.hip", "sls.hip", "batch.hip", "mlp.hip", "models.hip", "tiny.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

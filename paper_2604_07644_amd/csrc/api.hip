@@ -178,8 +178,16 @@ struct Solver : SolverBase {
   double last_rho = 1.0;
   bool solved_once = false;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // one-wavefront path for tiny problems (auto chunking, nx, nu <= 4, rows <= 8, N <= 63):
+  // FP64 copies of the problem and its result block
+  bool tiny = false;
+  TinyArgs ta{};
+  TinyOut* tout = nullptr;      // device
+  TinyOut* tout_h = nullptr;    // pinned
+  double tiny_prof[16] = {};    // phase counters of the one-wavefront path (see phase_cycles)
 
   ~Solver() override {
+    if (tout_h) (void)hipHostFree(tout_h);
     if (ctl_h) (void)hipHostFree(ctl_h);
     if (status_h) (void)hipHostFree(status_h);
     for (auto& e : ev)
@@ -294,6 +302,16 @@ struct Solver : SolverBase {
     for (double v : h.q) hn = std::max(hn, std::fabs(v));
     for (double v : h.r) hn = std::max(hn, std::fabs(v));
     hnorm = hn;
+    tiny = s.chunks_epoch == 0 && s.chunks_iter == 0 && tiny_fits(N, nx, nu, nc, nf);
+    if (tiny) {
+      ta.box = box_rows(h);
+      ta.A = up(h.A); ta.B = up(h.B); ta.b = up(h.b); ta.Q = up(h.Q); ta.R = up(h.R); ta.S = up(h.S);
+      ta.q = up(h.q); ta.r = up(h.r); ta.C = up(h.C); ta.D = up(h.D); ta.CN = up(h.CN);
+      ta.x0 = arena.alloc<double>(nx);
+      tout = arena.alloc<TinyOut>(1);
+      if (!arena.ok) return GSLS_ERR_OOM;
+      if (hipHostMalloc((void**)&tout_h, sizeof(TinyOut)) != hipSuccess) return GSLS_ERR_OOM;
+    }
     if (epoch_set_attributes<T>() != GSLS_OK) return GSLS_ERR_HIP;
     if (hipStreamSynchronize(stream) != hipSuccess) return GSLS_ERR_HIP;
     return GSLS_OK;
@@ -336,6 +354,7 @@ struct Solver : SolverBase {
             int warm_dev, gsls_result* res) override {
     if (!x0 || !(rho > 0.0) || !std::isfinite(rho) || !(tol >= 0.0)) return GSLS_ERR_INVALID_ARG;
     int rc;
+    if (tiny) return solve_tiny(x0, x0_dev, rho, tol, z0, y0, warm_dev, res);
     if ((rc = load_vec(x0d, x0, hd.nx, x0_dev))) return rc;
     if (z0 && y0) {
       if ((rc = load_vec(z, z0, hd.m, warm_dev))) return rc;
@@ -386,6 +405,74 @@ struct Solver : SolverBase {
     r.iterations = it; r.rho_updates = nupd; r.factorizations = nfact; r.rho = cur;
     r.ms_factor = ms_f; r.ms_iterate = ms_i; r.ms_total = ms_f + ms_i;
     last_rho = cur;
+    solved_once = true;
+    if (res) *res = r;
+    return GSLS_OK;
+  }
+
+  // Rows exactly [I 0; 0 I] at every stage and I at the terminal stage.
+  static int box_rows(const HostDesc& h) {
+    const int nx = h.nx, nu = h.nu, nc = h.nc;
+    if (nc != nx + nu || h.nf != nx) return 0;
+    for (int k = 0; k < h.N; ++k)
+      for (int r = 0; r < nc; ++r) {
+        for (int j = 0; j < nx; ++j)
+          if (h.C[((size_t)k * nc + r) * nx + j] != (r == j ? 1.0 : 0.0)) return 0;
+        for (int j = 0; j < nu; ++j)
+          if (h.D[((size_t)k * nc + r) * nu + j] != (r == nx + j ? 1.0 : 0.0)) return 0;
+      }
+    for (int r = 0; r < nx; ++r)
+      for (int j = 0; j < nx; ++j)
+        if (h.CN[(size_t)r * nx + j] != (r == j ? 1.0 : 0.0)) return 0;
+    return 1;
+  }
+
+  // The whole solve in one launch of the one-wavefront kernel (FP64).
+  int solve_tiny(const double* x0, int x0_dev, double rho, double tol, const double* z0, const double* y0,
+                 int warm_dev, gsls_result* res) {
+    int rc;
+    if ((rc = load_vec(const_cast<double*>(ta.x0), x0, hd.nx, x0_dev))) return rc;
+    if (z0 && y0) {
+      if ((rc = load_vec(z, z0, hd.m, warm_dev))) return rc;
+      if ((rc = load_vec(y, y0, hd.m, warm_dev))) return rc;
+    } else {
+      if (hipMemsetAsync(z, 0, sizeof(double) * hd.m, stream) != hipSuccess) return GSLS_ERR_HIP;
+      if (hipMemsetAsync(y, 0, sizeof(double) * hd.m, stream) != hipSuccess) return GSLS_ERR_HIP;
+    }
+    TinyArgs a = ta;
+    a.N = hd.N; a.nx = hd.nx; a.nu = hd.nu; a.nc = hd.nc; a.nf = hd.nf;
+    a.nlev = 1;
+    while ((1 << a.nlev) <= hd.N) ++a.nlev;
+    a.l = ld_; a.u = ud_; a.z = z; a.y = y; a.X = X; a.U = U;
+    a.rho0 = rho; a.tol = tol; a.rho_min = st.rho_min; a.rho_max = st.rho_max; a.rho_tol = st.rho_tol;
+    a.hnorm = hnorm; a.max_iter = st.max_iter; a.adaptive = st.adaptive_rho; a.sigma = st.sigma;
+    a.out = tout;
+    if (hipEventRecord(ev[0], stream) != hipSuccess) return GSLS_ERR_HIP;
+    if ((rc = launch_tiny(a, stream))) return rc;
+    if (hipEventRecord(ev[1], stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (hipMemcpyAsync(tout_h, tout, sizeof(TinyOut), hipMemcpyDeviceToHost, stream) != hipSuccess) return GSLS_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return GSLS_ERR_HIP;
+    const TinyOut o = *tout_h;
+    if (profile_on) {
+      tiny_prof[0] += 1.0;
+      tiny_prof[1] += (double)o.c_load;
+      tiny_prof[2] += (double)o.c_factor;
+      tiny_prof[3] += (double)o.c_iter;
+      tiny_prof[4] += (double)o.t_factor + (double)o.t_iter;
+      tiny_prof[5] += (double)o.nfact;
+      tiny_prof[6] += (double)o.it;
+    }
+    if (o.status == 6) return GSLS_ERR_NOT_PD;
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, ev[0], ev[1]);
+    gsls_result r{};
+    r.status = o.status == 1 ? GSLS_SOLVED : (o.status == 2 ? GSLS_MAX_ITER : GSLS_NUMERICAL_FAIL);
+    r.iterations = o.it; r.rho_updates = o.nupd; r.factorizations = o.nfact;
+    r.r_p = o.r_p; r.r_d = o.r_d; r.rho = o.rho; r.r_dyn = o.r_dyn;
+    r.ms_total = t;
+    r.ms_factor = (double)o.t_factor * 1e-5;   // 100 MHz counter -> ms
+    r.ms_iterate = (double)o.t_iter * 1e-5;
+    last_rho = o.rho;
     solved_once = true;
     if (res) *res = r;
     return GSLS_OK;
@@ -442,6 +529,16 @@ struct Solver : SolverBase {
       if (hipMemcpyAsync(ld_, h.l.data(), h.m * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess) ok = false;
       if (hipMemcpyAsync(ud_, h.u.data(), h.m * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess) ok = false;
     }
+    if (tiny) {   // the one-wavefront path's FP64 copies
+      auto putd = [&](const double* dst, const std::vector<double>& src) {
+        if (!src.empty() && hipMemcpyAsync(const_cast<double*>(dst), src.data(), src.size() * sizeof(double),
+                                           hipMemcpyHostToDevice, stream) != hipSuccess)
+          ok = false;
+      };
+      putd(ta.A, h.A); putd(ta.B, h.B); putd(ta.b, h.b); putd(ta.Q, h.Q); putd(ta.R, h.R); putd(ta.S, h.S);
+      putd(ta.q, h.q); putd(ta.r, h.r); putd(ta.C, h.C); putd(ta.D, h.D); putd(ta.CN, h.CN);
+      ta.box = box_rows(h);
+    }
     if (hipStreamSynchronize(stream) != hipSuccess || !ok) return GSLS_ERR_HIP;
     hd = h;
     double hn = 0.0;
@@ -473,7 +570,14 @@ struct Solver : SolverBase {
 
   int phase_cycles(int enable, double* out, int* chunks) override {
     if (enable >= 0) profile_on = enable != 0;
-    if (chunks) { chunks[0] = Pe; chunks[1] = Pi; chunks[2] = resident; chunks[3] = Lmax; }
+    if (chunks) {
+      if (tiny) { chunks[0] = 1; chunks[1] = 1; chunks[2] = 1; chunks[3] = hd.N; }
+      else { chunks[0] = Pe; chunks[1] = Pi; chunks[2] = resident; chunks[3] = Lmax; }
+    }
+    if (out && tiny) {
+      for (int i = 0; i < 16; ++i) { out[i] = tiny_prof[i]; tiny_prof[i] = 0.0; }
+      return GSLS_OK;
+    }
     if (out) {
       unsigned long long h[16];
       if (hipMemcpy(h, prof, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return GSLS_ERR_HIP;

@@ -117,6 +117,27 @@ int launch_sls_beta(const SlsArgs& args, hipStream_t st);
 int launch_sls_tau(int N, int nc, int nf, const float* betaj, const float* betafj, const double* lam, double eps,
                    double* tau, hipStream_t st);
 
+// One-wavefront solver of tiny problems (nx, nu <= 4, nc, nf <= 8, N <= 63):
+// a whole solve in FP64 in one launch.
+struct TinyOut {
+  int32_t it, status, nupd, nfact;   // status: 1 solved, 2 max_iter, 3 numerical, 6 not positive definite
+  double r_p, r_d, rho, r_dyn;
+  unsigned long long t_factor, t_iter;   // 100 MHz counter ticks
+  unsigned long long c_load, c_factor, c_iter;   // shader clock cycles: load, factors, iterations
+};
+struct TinyArgs {
+  int N, nx, nu, nc, nf, nlev;       // nlev: smallest L with 2^L > N
+  int box;                           // rows are [I 0; 0 I] per stage and I at the terminal stage (nf == nx)
+  const double *A, *B, *b, *Q, *R, *S, *q, *r, *C, *D, *CN, *l, *u, *x0;   // FP64, layout of the C ABI
+  double *z, *y;                     // [m] in: start iterate, out: last iterate
+  double *X, *U;                     // [N+1][nx], [N][nu]
+  double rho0, tol, rho_min, rho_max, rho_tol, hnorm;
+  int max_iter, adaptive, sigma;
+  TinyOut* out;
+};
+bool tiny_fits(int N, int nx, int nu, int nc, int nf);
+int launch_tiny(const TinyArgs& args, hipStream_t st);
+
 // Settings check shared by the entry points; descriptor validation with a
 // row limit of max_rows per stage (host descriptors only).
 int check_settings(const gsls_settings* s);

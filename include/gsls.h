@@ -50,7 +50,12 @@ enum {
 enum {
   GSLS_SOLVED = 1,           /* r_p <= tol and r_d <= tol                      */
   GSLS_MAX_ITER = 2,         /* iteration limit reached                         */
-  GSLS_NUMERICAL_FAIL = 3    /* NaN/Inf in the residuals                        */
+  GSLS_NUMERICAL_FAIL = 3,   /* NaN/Inf in the residuals                        */
+  GSLS_INFEASIBLE_SUSPECTED = 4  /* single-instance solves with adaptive rho: the
+                                    iteration limit was reached with r_p > tol after
+                                    the rho rule had raised rho to rho_max, the
+                                    pattern of ADMM on an infeasible QP (r_p settles
+                                    at the distance between the constraint sets) */
 };
 
 /* memory kinds */
@@ -106,11 +111,17 @@ typedef struct gsls_settings {
                             full after each factor epoch and, if refresh > 0,
                             at every iteration count that is a multiple of
                             refresh (bounds the FP32 drift of the accumulators) */
+  int32_t fp64_fallback; /* 1: a mixed-precision single-instance solve that    [0]
+                            reaches max_iter above tol is continued in FP64 from
+                            its last iterate (z, y, rho), with a fresh iteration
+                            budget, on an FP64 copy of the problem made on first
+                            use; ignored by batched solves */
 } gsls_settings;
 
 /* Outcome of one solve. */
 typedef struct gsls_result {
-  int32_t status;        /* GSLS_SOLVED / GSLS_MAX_ITER / GSLS_NUMERICAL_FAIL     */
+  int32_t status;        /* GSLS_SOLVED / GSLS_MAX_ITER / GSLS_NUMERICAL_FAIL /
+                            GSLS_INFEASIBLE_SUSPECTED                            */
   int32_t iterations;    /* ADMM iterations (x-updates) performed                 */
   int32_t rho_updates;   /* number of rho changes (each costs a factor epoch)     */
   int32_t factorizations;/* factor epochs run                                     */
@@ -124,7 +135,9 @@ typedef struct gsls_result {
   int32_t cold_restart;  /* batched learned warm start: 1 if the instance did not
                             converge within the warm budget and was re-solved
                             from a cold start (its iterations include both)    */
-  int32_t reserved;
+  int32_t fallback;      /* 1 if a mixed-precision solve reached max_iter and was
+                            continued in FP64 (gsls_settings.fp64_fallback); its
+                            iterations, epochs and times include both parts   */
   double r_dyn;          /* max_k |x_{k+1} - A_k x_k - B_k u_k - b_k|_inf of the
                             returned iterate, evaluated in FP64 on the working-
                             precision stage data (mixed precision: non-zero at

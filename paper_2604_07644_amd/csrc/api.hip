@@ -185,6 +185,7 @@ struct Solver : SolverBase {
   TinyOut* tout = nullptr;      // device
   TinyOut* tout_h = nullptr;    // pinned
   double tiny_prof[16] = {};    // phase counters of the one-wavefront path (see phase_cycles)
+  std::unique_ptr<SolverBase> fb;   // FP64 solver of the same problem (fp64_fallback), created on first use
 
   ~Solver() override {
     if (tout_h) (void)hipHostFree(tout_h);
@@ -350,8 +351,64 @@ struct Solver : SolverBase {
     return GSLS_OK;
   }
 
+  // A solve, then the outcome's post-processing.  A solve that reaches the
+  // iteration limit with the primal residual above tol after the rho rule has
+  // raised rho to rho_max is reported as GSLS_INFEASIBLE_SUSPECTED: on an
+  // infeasible QP r_p settles at the distance between the sets and the rule
+  // keeps raising rho to its clamp.  Otherwise a mixed-precision solve that
+  // reached the limit is continued in FP64 from its last iterate when
+  // settings.fp64_fallback is set.
   int solve(const double* x0, int x0_dev, double rho, double tol, const double* z0, const double* y0,
             int warm_dev, gsls_result* res) override {
+    gsls_result r{};
+    int rc = solve_core(x0, x0_dev, rho, tol, z0, y0, warm_dev, &r);
+    if (rc) return rc;
+    auto suspect = [&](const gsls_result& q) {
+      return q.status == GSLS_MAX_ITER && st.adaptive_rho && q.rho >= st.rho_max && q.r_p > tol;
+    };
+    if (!suspect(r) && r.status == GSLS_MAX_ITER && !std::is_same<T, double>::value && !tiny && st.fp64_fallback) {
+      if ((rc = fallback_fp64(x0, x0_dev, tol, &r))) return rc;
+    }
+    if (suspect(r)) r.status = GSLS_INFEASIBLE_SUSPECTED;
+    if (res) *res = r;
+    return GSLS_OK;
+  }
+
+  // FP64 continuation of a stalled mixed-precision solve: an FP64 solver of the
+  // same problem (created on first use), warm-started from the mixed iterate
+  // (z, y at the final rho); its iterate replaces this handle's.
+  int fallback_fp64(const double* x0, int x0_dev, double tol, gsls_result* r) {
+    int rc;
+    if (!fb) {
+      gsls_settings s2 = st;
+      s2.precision = GSLS_FP64;
+      s2.fp64_fallback = 0;
+      auto* p = new (std::nothrow) Solver<double>();
+      if (!p) return GSLS_ERR_OOM;
+      fb.reset(p);
+      if ((rc = p->init(hd, s2, stream))) { fb.reset(); return rc; }
+    }
+    auto* f = static_cast<Solver<double>*>(fb.get());
+    gsls_result r2{};
+    if ((rc = f->solve_core(x0, x0_dev, r->rho, tol, z, y, 1, &r2))) return rc;
+    const size_t N = hd.N, nx = hd.nx, nu = hd.nu, m = hd.m;
+    if (hipMemcpyAsync(X, f->X, (N + 1) * nx * sizeof(double), hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+        (N * nu > 0 && hipMemcpyAsync(U, f->U, N * nu * sizeof(double), hipMemcpyDeviceToDevice, stream) != hipSuccess) ||
+        (m > 0 && hipMemcpyAsync(z, f->z, m * sizeof(double), hipMemcpyDeviceToDevice, stream) != hipSuccess) ||
+        (m > 0 && hipMemcpyAsync(y, f->y, m * sizeof(double), hipMemcpyDeviceToDevice, stream) != hipSuccess) ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return GSLS_ERR_HIP;
+    last_rho = r2.rho;
+    r->status = r2.status;
+    r->iterations += r2.iterations; r->rho_updates += r2.rho_updates; r->factorizations += r2.factorizations;
+    r->r_p = r2.r_p; r->r_d = r2.r_d; r->rho = r2.rho; r->r_dyn = r2.r_dyn;
+    r->ms_total += r2.ms_total; r->ms_factor += r2.ms_factor; r->ms_iterate += r2.ms_iterate;
+    r->fallback = 1;
+    return GSLS_OK;
+  }
+
+  int solve_core(const double* x0, int x0_dev, double rho, double tol, const double* z0, const double* y0,
+                 int warm_dev, gsls_result* res) {
     if (!x0 || !(rho > 0.0) || !std::isfinite(rho) || !(tol >= 0.0)) return GSLS_ERR_INVALID_ARG;
     int rc;
     if (tiny) return solve_tiny(x0, x0_dev, rho, tol, z0, y0, warm_dev, res);
@@ -501,6 +558,7 @@ struct Solver : SolverBase {
   // G = [C | D], bounds and the host description; the SLS copies are
   // refreshed on their next use.
   int update_data(const HostDesc& h) override {
+    fb.reset();
     if (h.N != hd.N || h.nx != hd.nx || h.nu != hd.nu || h.nc != hd.nc || h.nf != hd.nf) return GSLS_ERR_DIM;
     const int N = h.N, nx = h.nx, nu = h.nu, nc = h.nc, nxu = nx + nu;
     std::vector<std::vector<T>> keep;   // host sources of the asynchronous copies
@@ -550,6 +608,7 @@ struct Solver : SolverBase {
   }
 
   int update_bounds(const double* l, const double* u, int dev) override {
+    fb.reset();
     if (!l || !u) return GSLS_ERR_INVALID_ARG;
     std::vector<double> lh(hd.m), uh(hd.m);
     if (dev) {
@@ -878,6 +937,7 @@ void gsls_default_settings(gsls_settings* s) {
   s->chunks_epoch = 0;
   s->chunks_iter = 0;
   s->refresh = 0;
+  s->fp64_fallback = 0;
 }
 
 const char* gsls_strerror(int code) {
@@ -900,7 +960,8 @@ namespace gsls {
 int check_settings(const gsls_settings* s) {
   if (s->precision != GSLS_MIXED && s->precision != GSLS_FP64) return GSLS_ERR_INVALID_ARG;
   if (s->max_iter < 1 || s->sigma < 1 || !(s->rho_min > 0) || !(s->rho_max >= s->rho_min) ||
-      !(s->rho_tol > 1.0) || s->chunks_epoch < 0 || s->chunks_iter < 0 || s->chunks_iter > 256 || s->refresh < 0)
+      !(s->rho_tol > 1.0) || s->chunks_epoch < 0 || s->chunks_iter < 0 || s->chunks_iter > 256 || s->refresh < 0 ||
+      (s->fp64_fallback != 0 && s->fp64_fallback != 1))
     return GSLS_ERR_INVALID_ARG;
   return GSLS_OK;
 }

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgsls.so")
 
 OK = 0
 ERR_INVALID_ARG, ERR_DIM, ERR_NOT_PD, ERR_NUMERICAL, ERR_OOM, ERR_HIP, ERR_STATE = range(-1, -8, -1)
-SOLVED, MAX_ITER, NUMERICAL_FAIL = 1, 2, 3
+SOLVED, MAX_ITER, NUMERICAL_FAIL, INFEASIBLE_SUSPECTED = 1, 2, 3, 4
 HOST, DEVICE = 0, 1
 MIXED, FP64 = 0, 1
 
@@ -71,14 +71,14 @@ class Settings(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("max_iter", ct.c_int32), ("adaptive_rho", ct.c_int32),
                 ("sigma", ct.c_int32), ("rho_min", ct.c_double), ("rho_max", ct.c_double),
                 ("rho_tol", ct.c_double), ("chunks_epoch", ct.c_int32), ("chunks_iter", ct.c_int32),
-                ("refresh", ct.c_int32)]
+                ("refresh", ct.c_int32), ("fp64_fallback", ct.c_int32)]
 
 
 class Result(ct.Structure):
     _fields_ = [("status", ct.c_int32), ("iterations", ct.c_int32), ("rho_updates", ct.c_int32),
                 ("factorizations", ct.c_int32), ("r_p", ct.c_double), ("r_d", ct.c_double),
                 ("rho", ct.c_double), ("ms_total", ct.c_double), ("ms_factor", ct.c_double),
-                ("ms_iterate", ct.c_double), ("cold_restart", ct.c_int32), ("reserved", ct.c_int32),
+                ("ms_iterate", ct.c_double), ("cold_restart", ct.c_int32), ("fallback", ct.c_int32),
                 ("r_dyn", ct.c_double)]
 
     def asdict(self):

@@ -67,6 +67,17 @@ def test_setup_rejects_bad_input_before_touching_the_device():
     with pytest.raises(gsls.GslsError) as ei:
         gsls.QP(W.box_lq(), gsls.default_settings(precision=7))
     assert ei.value.code == gsls.ERR_INVALID_ARG
+    with pytest.raises(gsls.GslsError) as ei:
+        gsls.QP(W.box_lq(), gsls.default_settings(fp64_fallback=2))
+    assert ei.value.code == gsls.ERR_INVALID_ARG
+
+
+def test_settings_struct_matches_the_header():
+    s = gsls.default_settings()
+    assert s.fp64_fallback == 0 and s.refresh == 0
+    # 4 int32, 3 double, 4 int32 (the last one fp64_fallback): 56 bytes
+    assert ct.sizeof(gsls.Settings) == 56
+    assert gsls.Result.fallback.offset == gsls.Result.cold_restart.offset + 4
 
 
 def test_null_handle_calls_fail_cleanly():

@@ -45,6 +45,7 @@ struct TinyLds {
   double CC[kTW * kTS], DD[kTW * kTS], DC[kTW * kTS];   // C^T C, D^T D, D^T C per stage
   double P[kTW * kTS], K[kTW * kTS], Hm[kTW * kTS];      // P_k, K_k, -(Rhat + B^T P B)^{-1}
   double M[kTL][kTW * kTS];                              // suffix-scan maps per level
+  double lo[kTC * kTW], hi[kTC * kTW];                   // row bounds, slot-major (lane fastest)
   double sc[6][16];                                      // factor-step scratch
   int flag;
 };
@@ -297,7 +298,7 @@ __global__ void __launch_bounds__(kTW) k_tiny(TinyArgs a) {
   }
   __syncthreads();
   // general rows: C and D rows in registers (box rows need none)
-  double Cr[kTC][4], Dr[kTC][4], lo[kTC], hi[kTC], z[kTC], y[kTC];
+  double Cr[kTC][4], Dr[kTC][4], z[kTC], y[kTC];
   double qv[4], rv[4], bv[4], xz[4];
 #pragma unroll
   for (int i = 0; i < kTC; ++i) {
@@ -310,8 +311,8 @@ __global__ void __launch_bounds__(kTW) k_tiny(TinyArgs a) {
         Dr[i][j] = (on && stage && j < nu) ? a.D[((size_t)k * nc + i) * nu + j] : 0.0;
       }
     }
-    lo[i] = on ? a.l[row] : 0.0;
-    hi[i] = on ? a.u[row] : 0.0;
+    L.lo[i * kTW + k] = on ? a.l[row] : 0.0;
+    L.hi[i * kTW + k] = on ? a.u[row] : 0.0;
     z[i] = on ? a.z[row] : 0.0;
     y[i] = on ? a.y[row] : 0.0;
   }
@@ -493,7 +494,7 @@ __global__ void __launch_bounds__(kTW) k_tiny(TinyArgs a) {
           for (int j = 0; j < 4; ++j) v += Cr[i][j] * x[j] + Dr[i][j] * u[j];
         }
         const double t = v + y[i];
-        const double zn = fmin(fmax(t, lo[i]), hi[i]);
+        const double zn = fmin(fmax(t, L.lo[i * kTW + k]), L.hi[i * kTW + k]);
         const double dz = zn - z[i];
         const double rr = v - zn;
         y[i] += rr;

@@ -255,7 +255,10 @@ class QP:
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:   # interpreter teardown: the module's globals may already be gone
+            pass
 
     def update_bounds(self, l, u):
         l = _f64(l); u = _f64(u)
@@ -387,7 +390,10 @@ class SQP:
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:   # interpreter teardown: the module's globals may already be gone
+            pass
 
     def _check_traj(self, X, U, x0):
         X = np.array(X, dtype=np.float64); U = np.array(U, dtype=np.float64)
@@ -463,7 +469,10 @@ class Batch:
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:   # interpreter teardown: the module's globals may already be gone
+            pass
 
     def solve(self, x0s=None, rhos=1.0, tol=1e-5, z0s=None, y0s=None):
         n = len(self.probs)
@@ -600,7 +609,10 @@ class WarmStart:
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:   # interpreter teardown: the module's globals may already be gone
+            pass
 
     def params(self):
         p = np.zeros(self.nparams(), dtype=np.float32)

@@ -308,7 +308,6 @@ struct Solver : SolverBase {
       ta.box = box_rows(h);
       ta.A = up(h.A); ta.B = up(h.B); ta.b = up(h.b); ta.Q = up(h.Q); ta.R = up(h.R); ta.S = up(h.S);
       ta.q = up(h.q); ta.r = up(h.r); ta.C = up(h.C); ta.D = up(h.D); ta.CN = up(h.CN);
-      ta.x0 = arena.alloc<double>(nx);
       tout = arena.alloc<TinyOut>(1);
       if (!arena.ok) return GSLS_ERR_OOM;
       if (hipHostMalloc((void**)&tout_h, sizeof(TinyOut)) != hipSuccess) return GSLS_ERR_OOM;
@@ -488,15 +487,23 @@ struct Solver : SolverBase {
   int solve_tiny(const double* x0, int x0_dev, double rho, double tol, const double* z0, const double* y0,
                  int warm_dev, gsls_result* res) {
     int rc;
-    if ((rc = load_vec(const_cast<double*>(ta.x0), x0, hd.nx, x0_dev))) return rc;
-    if (z0 && y0) {
+    TinyArgs a = ta;
+    // x0 travels in the kernel arguments; a cold start is cleared in the kernel
+    double xh[4] = {0.0, 0.0, 0.0, 0.0};
+    if (x0_dev) {
+      if (hipMemcpy(xh, x0, hd.nx * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return GSLS_ERR_HIP;
+    } else {
+      std::memcpy(xh, x0, hd.nx * sizeof(double));
+    }
+    for (int j = 0; j < hd.nx; ++j) {
+      if (!std::isfinite(xh[j])) return GSLS_ERR_INVALID_ARG;
+      a.x0v[j] = xh[j];
+    }
+    a.cold = (z0 && y0) ? 0 : 1;
+    if (!a.cold) {
       if ((rc = load_vec(z, z0, hd.m, warm_dev))) return rc;
       if ((rc = load_vec(y, y0, hd.m, warm_dev))) return rc;
-    } else {
-      if (hipMemsetAsync(z, 0, sizeof(double) * hd.m, stream) != hipSuccess) return GSLS_ERR_HIP;
-      if (hipMemsetAsync(y, 0, sizeof(double) * hd.m, stream) != hipSuccess) return GSLS_ERR_HIP;
     }
-    TinyArgs a = ta;
     a.N = hd.N; a.nx = hd.nx; a.nu = hd.nu; a.nc = hd.nc; a.nf = hd.nf;
     a.nlev = 1;
     while ((1 << a.nlev) <= hd.N) ++a.nlev;

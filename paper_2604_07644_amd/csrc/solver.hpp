@@ -128,8 +128,10 @@ struct TinyOut {
 struct TinyArgs {
   int N, nx, nu, nc, nf, nlev;       // nlev: smallest L with 2^L > N
   int box;                           // rows are [I 0; 0 I] per stage and I at the terminal stage (nf == nx)
-  const double *A, *B, *b, *Q, *R, *S, *q, *r, *C, *D, *CN, *l, *u, *x0;   // FP64, layout of the C ABI
-  double *z, *y;                     // [m] in: start iterate, out: last iterate
+  const double *A, *B, *b, *Q, *R, *S, *q, *r, *C, *D, *CN, *l, *u;   // FP64, layout of the C ABI
+  double x0v[4];                     // initial state (first nx entries)
+  int cold;                          // 1: start from z = y = 0 (z, y are not read)
+  double *z, *y;                     // [m] in: start iterate (cold == 0), out: last iterate
   double *X, *U;                     // [N+1][nx], [N][nu]
   double rho0, tol, rho_min, rho_max, rho_tol, hnorm;
   int max_iter, adaptive, sigma;

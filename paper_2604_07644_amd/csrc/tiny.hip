@@ -313,15 +313,15 @@ __global__ void __launch_bounds__(kTW) k_tiny(TinyArgs a) {
     }
     L.lo[i * kTW + k] = on ? a.l[row] : 0.0;
     L.hi[i * kTW + k] = on ? a.u[row] : 0.0;
-    z[i] = on ? a.z[row] : 0.0;
-    y[i] = on ? a.y[row] : 0.0;
+    z[i] = (on && !a.cold) ? a.z[row] : 0.0;
+    y[i] = (on && !a.cold) ? a.y[row] : 0.0;
   }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     qv[j] = (k <= N && j < nx) ? a.q[(size_t)k * nx + j] : 0.0;
     rv[j] = (stage && j < nu) ? a.r[(size_t)k * nu + j] : 0.0;
     bv[j] = (stage && j < nx) ? a.b[(size_t)k * nx + j] : 0.0;
-    xz[j] = (k == 0 && j < nx) ? a.x0[j] : 0.0;
+    xz[j] = (k == 0 && j < nx) ? a.x0v[j] : 0.0;
   }
   if (k <= N) {
 #pragma unroll
@@ -616,13 +616,15 @@ __global__ void __launch_bounds__(kTW) k_tiny(TinyArgs a) {
       for (int j = 0; j < nx; ++j) a.X[(size_t)k * nx + j] = x[j];
     if (stage)
       for (int t = 0; t < nu; ++t) a.U[(size_t)k * nu + t] = u[t];
+  }
+  // the iterate (z, y) is written also when a factor failed: a cold start
+  // leaves zeros, as the solver state before the first iteration
 #pragma unroll
-    for (int i = 0; i < kTC; ++i) {
-      const int row = tiny_row<BOX>(i, k, N, nx, nu, nc, nf);
-      if (row >= 0) {
-        a.z[row] = z[i];
-        a.y[row] = y[i];
-      }
+  for (int i = 0; i < kTC; ++i) {
+    const int row = tiny_row<BOX>(i, k, N, nx, nu, nc, nf);
+    if (row >= 0) {
+      a.z[row] = z[i];
+      a.y[row] = y[i];
     }
   }
   if (k == 0) {

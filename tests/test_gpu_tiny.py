@@ -148,3 +148,47 @@ def test_indefinite_control_block_is_reported():
         q.solve(rho=1e-3, tol=1e-6)
     assert ei.value.code == gsls.ERR_NOT_PD
     q.close()
+
+
+def test_device_descriptor_matches_host():
+    """Problem data, x0 and the warm start in device memory (GSLS_DEVICE) on the
+    one-wavefront path: the same FP64 solves, bit for bit, as from host memory."""
+    import torch
+    p = PROBLEMS["general_4x3"]()
+    s = gsls.default_settings(precision=gsls.FP64)
+    q = gsls.QP(p, s)
+    rh = q.solve(rho=1.0, tol=1e-7)
+    gh = q.get()
+    rhw = q.solve(rho=rh["rho"], tol=1e-9, z0=gh["z"], y0=gh["lam"] / rh["rho"])
+    ghw = q.get()
+    q.close()
+
+    def dev(a):
+        return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+    def dptr(t):
+        return ct.cast(ct.c_void_p(t.data_ptr()), ct.POINTER(ct.c_double))
+
+    keep = {k: dev(getattr(p, k)) for k in ("A", "B", "b", "Q", "R", "S", "q", "r", "C", "D", "l", "u")}
+    keep["CN"] = dev(np.asarray(p.CN).reshape(p.nf, p.nx))
+    d = gsls.QPDesc(N=p.N, nx=p.nx, nu=p.nu, nc=p.nc, nf=p.nf, mem=gsls.DEVICE)
+    for k, t in keep.items():
+        setattr(d, k, dptr(t))
+    h = ct.c_void_p()
+    assert gsls.lib.gsls_qp_setup(ct.byref(d), ct.byref(s), None, ct.byref(h)) == gsls.OK
+    lay = (ct.c_int32 * 4)()
+    assert gsls.lib.gsls_debug_phase_cycles(h, -1, None, lay) == gsls.OK and tuple(lay) == (1, 1, 1, p.N)
+    x0 = dev(p.x0)
+    r = gsls.Result()
+    assert gsls.lib.gsls_qp_solve(h, dptr(x0), 1.0, 1e-7, ct.byref(r)) == gsls.OK
+    X = np.zeros((p.N + 1, p.nx)); z = np.zeros(p.m); lam = np.zeros(p.m)
+    P = ct.POINTER(ct.c_double)
+    assert gsls.lib.gsls_qp_get(h, X.ctypes.data_as(P), None, z.ctypes.data_as(P), lam.ctypes.data_as(P)) == gsls.OK
+    assert r.iterations == rh["iterations"] and r.rho_updates == rh["rho_updates"]
+    np.testing.assert_array_equal(X, gh["X"])
+    z0, y0 = dev(z), dev(lam / r.rho)
+    assert gsls.lib.gsls_qp_solve_warm(h, dptr(x0), r.rho, 1e-9, dptr(z0), dptr(y0), ct.byref(r)) == gsls.OK
+    assert gsls.lib.gsls_qp_get(h, X.ctypes.data_as(P), None, None, None) == gsls.OK
+    assert r.iterations == rhw["iterations"]
+    np.testing.assert_array_equal(X, ghw["X"])
+    gsls.lib.gsls_qp_free(h)

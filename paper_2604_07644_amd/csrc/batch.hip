@@ -36,7 +36,22 @@ constexpr int kBatchMaxNxu = 96;
 constexpr int kGangMax = 32;          // workgroups per gang (6 kGangMax <= kWG: residual exchange)
 constexpr int kGangAuto = 32;
 constexpr double kParkShareAuto = 1.0;
-constexpr double kParkResid = 10.0;   // no hand-over once r_p, r_d <= kParkResid * tol
+// No hand-over once r_p, r_d <= kParkResid * tol: at the solo budget the
+// residual's distance from the stopping test tracks the iterations still to
+// run, and an instance this close finishes solo in fewer workgroup-seconds
+// (and sooner) than a gang that must first assemble.
+constexpr double kParkResid = 30.0;
+// A hand-over whose rho is at least kPrioRho and has grown at least
+// kPrioGrowth-fold since the start, with a residual still at least
+// kPrioResid * tol, goes to the priority list, whose gangs are filled first:
+// a penalty parameter driven up by the residual balance together with a
+// residual far from the stopping test marks the ill-conditioned instances
+// that run for many more iterations than the rest of the batch (its
+// makespan).  A high rho that was the start value (a learned start) says less
+// about the remaining iterations.
+constexpr double kPrioRho = 50.0;
+constexpr double kPrioGrowth = 4.0;
+constexpr double kPrioResid = 300.0;
 
 __host__ __device__ inline int bodd(int x) { return x | 1; }
 
@@ -1691,6 +1706,8 @@ struct BSync {
   unsigned cont;        // instances handed to gangs (slots reserved)
   unsigned done;        // solo items finished (solved or handed over)
   int abort;            // a bounded wait gave up
+  unsigned pticket;     // gang tickets of the priority list
+  unsigned pcont;       // instances handed to the priority list
 };
 
 __device__ inline void g_publish(unsigned long long* w, uint32_t stamp, const LDS float* v, int n) {
@@ -2057,6 +2074,7 @@ __device__ __attribute__((noinline)) void batch_solo(const BatchArgs* __restrict
     for (int r = tid(); r < m; r += kWG) { a.dp[oz + r] = 0.0; a.dp[oy + r] = 0.0; }
   __syncthreads();
   double rho = a.rho0[idx];
+  double rho_start = rho;
   int it = 0, nupd = 0, nfact = 0, st = 0, restarted = 0;
   double rp = 0.0, rd = 0.0;
   const bool budgeted = warm && a.warm_budget > 0 && a.warm_budget < a.max_iter;
@@ -2080,7 +2098,7 @@ __device__ __attribute__((noinline)) void batch_solo(const BatchArgs* __restrict
       restarted = 1;
       it0 = it;
       limit = it + a.max_iter;
-      rho = a.rho_cold;
+      rho = rho_start = a.rho_cold;
       for (int r = tid(); r < m; r += kWG) { a.dp[oz + r] = 0.0; a.dp[oy + r] = 0.0; }
       __syncthreads();
       continue;
@@ -2097,8 +2115,12 @@ __device__ __attribute__((noinline)) void batch_solo(const BatchArgs* __restrict
       pk.rho = rho; pk.te = te; pk.ti = ti;
       a.park[idx] = pk;
       __threadfence();
-      const unsigned slot = atomicAdd(&sy->cont, 1u);
-      atomicExch(a.cont_list + slot, idx);
+      // priority slots fill cont_list from the front, the others from the
+      // back (an instance is handed over at most once per launch)
+      const bool prio = rho >= kPrioRho && rho >= kPrioGrowth * rho_start &&
+                        (rp >= kPrioResid * a.tol || rd >= kPrioResid * a.tol);
+      const unsigned slot = atomicAdd(prio ? &sy->pcont : &sy->cont, 1u);
+      atomicExch(a.cont_list + (prio ? slot : (unsigned)a.count - 1u - slot), idx);
     }
   } else if (tid() == 0) {
     BResult r;
@@ -2116,17 +2138,43 @@ __device__ __attribute__((noinline)) void batch_solo(const BatchArgs* __restrict
   __syncthreads();
 }
 
-// Persistent batched solver.  A free workgroup first joins a gang whose
-// instance has been handed over and still lacks members (so a handed-over
-// instance waits only for the solo items running when it was handed over),
-// else takes the next solo instance from the work queue (largest first),
-// else waits for hand-overs until every solo item has finished.  Gang tickets
-// are consecutive per handed-over instance (G per instance, in hand-over
-// order); a ticket is taken only for an instance already handed over while
-// solo items remain, so no workgroup waits on an instance that may never
-// come while runnable work is queued.  A gang is complete before any later
-// ticket is taken, hence a gang waits only for workgroups busy elsewhere
-// (G <= grid).
+// Thread 0: a seat in the gang of a handed-over instance of one hand-over
+// list, if one is open (a ticket below cont * G).  Tickets are consecutive
+// per listed instance (G per instance, in hand-over order), so a gang's seats
+// are all taken before any seat of a later gang of the same list.  The list's
+// slot i is cont_list[i] (front) or cont_list[count - 1 - i].  True if a
+// ticket was taken; *code is then the seat (instance << 8 | rank), or left as
+// it was after raising the abort flag if the slot's entry never appeared.
+__device__ inline bool take_seat(const BatchArgs& a, unsigned* ticket, const unsigned* cont, bool front, int G,
+                                 int* code) {
+  unsigned tk = __hip_atomic_load(ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  while (true) {
+    const unsigned cn = __hip_atomic_load(cont, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tk >= cn * (unsigned)G) return false;
+    if (__hip_atomic_compare_exchange_strong(ticket, &tk, tk + 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT)) {
+      const unsigned slot = tk / (unsigned)G;
+      const int* e = a.cont_list + (front ? slot : (unsigned)a.count - 1u - slot);
+      int v = -1;
+      unsigned n = 0;
+      // the slot is reserved: its entry is being written
+      while ((v = __hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < 0 && ++n < kSpinLimit)
+        __builtin_amdgcn_s_sleep(1);
+      if (v < 0) __hip_atomic_store(&a.sync->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      else *code = (v << 8) | (int)(tk % (unsigned)G);
+      return true;
+    }
+  }
+}
+
+// Persistent batched solver.  A free workgroup first takes an open seat in
+// the gang of a handed-over instance (priority list first, then the other),
+// else the next solo instance from the work queue (largest first), else it
+// waits for a seat to open until every solo item has finished.  A seat is
+// taken only once its instance has been handed over, so no workgroup waits on
+// an instance that may never come.  At most one gang per list has seats both
+// taken and open (tickets are consecutive per list), every other workgroup
+// runs work that ends, and G <= grid / 2, so both partial gangs fill.
 __global__ void __launch_bounds__(kWG) k_batch(const BatchArgs* __restrict__ ag) {
   extern __shared__ __align__(16) char lds_generic[];
   LDS char* base = (LDS char*)lds_generic;
@@ -2140,28 +2188,10 @@ __global__ void __launch_bounds__(kWG) k_batch(const BatchArgs* __restrict__ ag)
     if (tid() == 0) {
       int code = -1 - (int)count;
       bool decided = false;
-      if (G > 1) {
-        // 1. an open seat in a handed-over instance's gang
-        unsigned tk = __hip_atomic_load(&sy->ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        while (true) {
-          const unsigned cn = __hip_atomic_load(&sy->cont, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (tk >= cn * (unsigned)G) break;
-          if (__hip_atomic_compare_exchange_strong(&sy->ticket, &tk, tk + 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT)) {
-            const unsigned slot = tk / (unsigned)G;
-            int v = -1;
-            unsigned n = 0;
-            // the slot is reserved: its entry is being written
-            while ((v = __hip_atomic_load(a.cont_list + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < 0 &&
-                   ++n < kSpinLimit)
-              __builtin_amdgcn_s_sleep(1);
-            if (v < 0) __hip_atomic_store(&sy->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            else code = (v << 8) | (int)(tk % (unsigned)G);
-            decided = true;
-            break;
-          }
-        }
-      }
+      // 1. an open seat in a handed-over instance's gang
+      if (G > 1)
+        decided = take_seat(a, &sy->pticket, &sy->pcont, true, G, &code) ||
+                  take_seat(a, &sy->ticket, &sy->cont, false, G, &code);
       if (!decided) {
         // 2. the next solo item
         const unsigned item = atomicAdd(&sy->counter, 1u);
@@ -2171,25 +2201,23 @@ __global__ void __launch_bounds__(kWG) k_batch(const BatchArgs* __restrict__ ag)
         }
       }
       if (!decided && G > 1) {
-        // 3. no solo work left: wait for the next hand-over, or for the end
-        const unsigned tk = atomicAdd(&sy->ticket, 1u);
-        const unsigned slot = tk / (unsigned)G;
-        if (slot < count) {
-          unsigned n = 0;
-          while (true) {
-            const int v = __hip_atomic_load(a.cont_list + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (v >= 0) { code = (v << 8) | (int)(tk % (unsigned)G); break; }
-            const unsigned dn = __hip_atomic_load(&sy->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
-            const unsigned cn = __hip_atomic_load(&sy->cont, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (dn >= count && slot >= cn) break;
-            if (__hip_atomic_load(&sy->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-            if (++n > 64u * kSpinLimit) {
-              __hip_atomic_store(&sy->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              break;
-            }
-            __builtin_amdgcn_s_sleep(8);
+        // 3. no solo work left: wait for a seat, or for the end.  A hand-over
+        // reserves its slot before its solo item counts as done, so once every
+        // solo item is done the lists read after that are final.
+        unsigned n = 0;
+        while (true) {
+          const unsigned dn = __hip_atomic_load(&sy->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __threadfence();
+          if (take_seat(a, &sy->pticket, &sy->pcont, true, G, &code) ||
+              take_seat(a, &sy->ticket, &sy->cont, false, G, &code))
+            break;
+          if (dn >= count) break;
+          if (__hip_atomic_load(&sy->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+          if (++n > 64u * kSpinLimit) {
+            __hip_atomic_store(&sy->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
           }
+          __builtin_amdgcn_s_sleep(8);
         }
       }
       s_code = code;
@@ -2253,6 +2281,7 @@ __global__ void k_batch_prologue(BSync* sync, int* cont_list, unsigned* join, in
   const int i = blockIdx.x * blockDim.x + tid();
   if (i == 0) {
     sync->counter = 0u; sync->ticket = 0u; sync->cont = 0u; sync->done = 0u; sync->abort = 0;
+    sync->pticket = 0u; sync->pcont = 0u;
   }
   if (i < count) { cont_list[i] = -1; join[i] = 0u; }
 }

@@ -63,7 +63,7 @@ struct BatchArgs {
   // gangs (continuation of instances over several workgroups)
   int gang;                    // workgroups per gang (<= 1: no gangs)
   struct BSync* sync;          // launch counters (cleared by the prologue)
-  int* cont_list;              // [count] instances handed to gangs, in order
+  int* cont_list;              // [count] instances handed to gangs: priority list from the front, the other from the back
   unsigned* join;              // [count] gang join counters
   struct BPark* park;          // [count] control state at hand-over
   unsigned long long* gwords;  // exchange words (per instance at BInst::ogw)

@@ -50,8 +50,8 @@ K_ADMM_TRAFFIC = {
                  "bytes_per_launch": 1.4470e10},
 }
 # The same for k_batch on the 512-instance batch (learned warm start, predicted rho0).
-K_BATCH_TRAFFIC = {"src_sha256_16": "945a2883c9722e65", "sources": ("batch.hip", "batch.hpp", "dev_common.hpp"),
-                   "bytes_per_launch": 1.1460e12}
+K_BATCH_TRAFFIC = {"src_sha256_16": "66f29ffb6c8faca7", "sources": ("batch.hip", "batch.hpp", "dev_common.hpp"),
+                   "bytes_per_launch": 1.1720e12}
 
 
 def kernel_traffic(entry):

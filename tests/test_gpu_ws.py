@@ -227,6 +227,37 @@ def test_trained_model_gain_on_held_out_batch():
     b.close(); ws.close()
 
 
+def test_learned_start_faster_than_cold_on_uneven_batch():
+    """The learned start (predicted rho0, z0 = y0 = 0) solves the 512-instance
+    uneven batch in less device time than the cold start, prediction
+    included, under the batch's tuned gang schedule; every instance of both
+    runs meets the stopping test.  Best of three replays each after a warm-up
+    (measured margin about 12 %)."""
+    import os
+    from paper_2604_07644_amd import autotune
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2604_07644_amd", "data", "ws_box.bin")
+    ws = gsls.WarmStart(path=path)
+    probs = W.uneven_batch(count=512)
+    b = gsls.Batch(probs)
+    tuned = autotune.lookup(autotune.batch_key(probs))
+    if tuned is not None:
+        b.set_schedule(gang=tuned["gang"], park_share=tuned["park_share"])
+    b.solve(tol=1e-5)
+    b.solve_ws(ws, tol=1e-5, parts=gsls.WS_RHO)
+    cold, warm = [], []
+    for _ in range(3):
+        r, ms = b.solve(tol=1e-5)
+        assert all(x["status"] == gsls.SOLVED for x in r)
+        cold.append(ms)
+        r, ms, _ = b.solve_ws(ws, tol=1e-5, parts=gsls.WS_RHO)
+        assert all(x["status"] == gsls.SOLVED for x in r)
+        warm.append(ms)
+    print(f"cold {min(cold):.1f} ms, learned start {min(warm):.1f} ms (device, per batch)")
+    assert min(warm) < min(cold), (warm, cold)
+    b.close(); ws.close()
+
+
 def test_warm_start_parts():
     """The start may take any subset of the prediction: with the predicted
     rho alone (z0 = y0 = 0) the same optimum is reached, and a warm budget of

@@ -383,14 +383,17 @@ void gsls_batch_free(gsls_batch* b);
 
 /* Schedule of the batched launch (Sec. IV-A: the horizon of one instance is
  * split into chunks whose affine maps are composed by associative scans).
- * Every instance starts on one workgroup; an instance with N >= 2 gang that
- * has not converged after park_at iterations is continued by a gang of
+ * Every instance starts on one workgroup; an instance with N >= 2 gang whose
+ * r_p or r_d is still above 30 tol after park_at iterations is continued by a gang of
  * `gang` workgroups, each owning N / gang consecutive stages (chunk fold,
  * recursive doubling over the chunk transfer maps, re-run from the exact
  * entry).  park_at is the iteration count at which the instance's estimated
  * solo work reaches park_share times one workgroup's share of the batch
- * (every instance at 100 iterations); it depends on the shapes only, so a
- * replay takes the same path.
+ * (every instance at 100 iterations); it depends on the shapes only.  Gangs
+ * are filled first for hand-overs whose rho has reached 50 and grown at least
+ * 4-fold since the instance's start while r_p or r_d is still at least 300 tol
+ * (the instances that set the batch's makespan), then for the rest, each in
+ * hand-over order.
  *  gang: 0 = automatic (32), 1 = no gangs, 2..32 (at most half the grid).
  *  park_share: > 0, or 0 = automatic (1.0).
  * Drops the captured launch (the next solve captures a new one). */
